@@ -1,0 +1,789 @@
+/*
+ * kc_oracle.c -- CPU oracle for exact k-clique counting.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product path never does.  It
+ * shares no code, header, table or helper with the GPU library.
+ *
+ * Graphs are simple undirected graphs in CSR form: row_ptr[n+1] and
+ * col[row_ptr[n]] (int32), rows sorted ascending, symmetric, no loops.
+ *
+ * Contents and where each piece comes from in the paper
+ * ("Efficient k-clique Listing with Set Intersection Speedup"):
+ *
+ *   orc_binom            C(n, k) exactly, with overflow detection (used for
+ *                        the clique components of Pre-List, Sec. 5.2).
+ *   orc_count_brute      plain definition of the result (Def. 2 and the
+ *                        problem statement of Sec. 3.1): every k-subset is
+ *                        tested for pairwise adjacency.  n <= 30.
+ *   orc_count_idorder    the same result by the textbook ordered recursion
+ *                        (the kClist scheme of Alg. 2 with eta = vertex id):
+ *                        each clique is counted once, from its smallest id.
+ *                        Optional per-vertex participation counts.
+ *   orc_vertex_count     per-vertex participation of one vertex v: the number
+ *                        of (k-1)-cliques in the subgraph induced by N(v).
+ *   orc_core_numbers     core numbers by the bucket algorithm of Batagelj and
+ *                        Zaversnik (the "classic core decomposition" the
+ *                        paper cites for degeneracy, Sec. 3).
+ *   orc_precore          Pre-Core, Alg. 3 (queue-based (k-1)-core peel).
+ *   orc_prelist          Pre-List, Alg. 4 (components that are cliques).
+ *   orc_degree_dag       degree ordering of Sec. 6.2: u -> v iff
+ *                        (d_u, u) < (d_v, v) on the reduced graph.
+ *   orc_degeneracy_dag   degeneracy ordering (Sec. 7.4) as a synchronous peel.
+ *   orc_sdegree_dag      SDegree, Alg. 5, instrumented per root.
+ *   orc_greedy_color     greedy coloring in inverse degree order (Sec. 7.1).
+ *   orc_bitcol_dag       BitCol, Alg. 6, instrumented per root.
+ *
+ * Readings of passages that are ambiguous or garbled in the paper:
+ *   - Pre-Core removes vertices of degree < k-1 (Alg. 3), keeping the
+ *     (k-1)-core.
+ *   - Pre-List's clique test counts adjacency entries in both directions:
+ *     a component with n_c vertices is a clique iff its degree sum equals
+ *     n_c (n_c - 1).  It contributes C(n_c, k) cliques and C(n_c-1, k-1) to
+ *     each member.
+ *   - Degree ordering uses the degrees of the graph left by Pre-Core and
+ *     Pre-List; ties go to the smaller vertex id.
+ *   - Degeneracy ordering: a synchronous peel.  Level c starts at 0; each
+ *     round removes every live vertex of live degree <= c at once and gives
+ *     them the next round number; when a round finds nothing, c grows by one.
+ *     u -> v iff (round_u, u) < (round_v, v).  Out-degree <= core number.
+ *   - Greedy coloring order: descending degree inside G_u, ties by ascending
+ *     vertex id; colors are 1-based; a vertex takes the smallest color not
+ *     used by an already-colored neighbour.
+ *   - BitCol bitmaps: bit i of word j stands for local vertex j*L + i (least
+ *     significant bit first, as in the paper's encoding table); local vertices
+ *     are the members of N+(u) in ascending id order; B(v) holds the
+ *     neighbours of v in G_u of strictly smaller color.
+ *   - Work per root: `nodes` counts calls of the listing procedure (the top
+ *     call included), `isect` counts set intersections (merge joins or
+ *     BitJoins), `elems` adds |C| + d+_u per merge join (the cost term of
+ *     Lemma 2) and `words` adds ceil(s / 32) per BitJoin.
+ */
+#define _POSIX_C_SOURCE 199309L
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EOVERFLOW (-3)
+#define ORC_EBUDGET (-6)
+
+typedef unsigned __int128 u128;
+
+static int add_checked(uint64_t* acc, uint64_t x) {
+  uint64_t s = *acc + x;
+  if (s < *acc) return 1;
+  *acc = s;
+  return 0;
+}
+
+/* ----------------------------------------------------------- binomial */
+int orc_binom(uint64_t n, uint64_t k, uint64_t* out) {
+  if (k > n) { *out = 0; return ORC_OK; }
+  if (k > n - k) k = n - k;
+  /* r_i = C(n-k+i, i); r_i = r_{i-1} * (n-k+i) / i is exact */
+  u128 r = 1;
+  for (uint64_t i = 1; i <= k; ++i) {
+    r = r * (u128)(n - k + i);
+    r /= i;
+    if (r > (u128)UINT64_MAX) return ORC_EOVERFLOW;
+  }
+  *out = (uint64_t)r;
+  return ORC_OK;
+}
+
+/* ---------------------------------------------------- input validation */
+int orc_validate(int32_t n, const int32_t* rp, const int32_t* col) {
+  if (n < 0) return ORC_EINVAL;
+  if (n == 0) return ORC_OK;
+  if (rp[0] != 0) return ORC_EINVAL;
+  for (int32_t v = 0; v < n; ++v) {
+    if (rp[v + 1] < rp[v]) return ORC_EINVAL;
+    for (int32_t i = rp[v]; i < rp[v + 1]; ++i) {
+      int32_t w = col[i];
+      if (w < 0 || w >= n || w == v) return ORC_EINVAL;
+      if (i > rp[v] && col[i - 1] >= w) return ORC_EINVAL;
+      /* symmetry: v must appear in w's row (binary search) */
+      int32_t lo = rp[w], hi = rp[w + 1];
+      while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (col[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= rp[w + 1] || col[lo] != v) return ORC_EINVAL;
+    }
+  }
+  return ORC_OK;
+}
+
+/* ----------------------------------------------------- O0: brute force */
+int orc_count_brute(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, uint64_t* count,
+                    uint64_t* pv) {
+  if (n < 0 || n > 30 || k < 1) return ORC_EINVAL;
+  uint32_t adj[30];
+  for (int32_t v = 0; v < n; ++v) {
+    adj[v] = 0;
+    for (int32_t i = rp[v]; i < rp[v + 1]; ++i) adj[v] |= 1u << col[i];
+  }
+  if (pv)
+    for (int32_t v = 0; v < n; ++v) pv[v] = 0;
+  *count = 0;
+  if (k > n) return ORC_OK;
+  /* walk all k-subsets of {0..n-1} as bit masks in increasing order */
+  uint64_t s = (k == 0) ? 0 : ((uint64_t)1 << k) - 1;
+  uint64_t limit = (uint64_t)1 << n;
+  while (s < limit) {
+    int ok = 1;
+    for (int32_t v = 0; v < n && ok; ++v)
+      if ((s >> v) & 1) {
+        uint32_t others = (uint32_t)s & ~(1u << v);
+        if ((others & adj[v]) != others) ok = 0;
+      }
+    if (ok) {
+      (*count)++;
+      if (pv)
+        for (int32_t v = 0; v < n; ++v)
+          if ((s >> v) & 1) pv[v]++;
+    }
+    /* next subset of the same size (Gosper) */
+    uint64_t c = s & (~s + 1), r = s + c;
+    s = (((r ^ s) >> 2) / c) | r;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------ O1: ordered recursion by id */
+typedef struct {
+  const int32_t* rp;
+  const int32_t* col;
+  uint64_t* pv;
+  int32_t* R;      /* chosen vertices, R[0..depth) */
+  int32_t* buf;    /* candidate lists, one block per depth */
+  int32_t stride;  /* block size (max degree + 1) */
+  uint64_t budget; /* max intersections (0 = unlimited) */
+  uint64_t isects;
+  double deadline; /* CLOCK_MONOTONIC seconds (0 = none) */
+  int status;
+} idrec_t;
+
+static double mono_now(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* out = {w in N(v) : w > v} intersected with cand[0..len); returns |out| */
+static int32_t isect_up(const idrec_t* S, int32_t v, const int32_t* cand, int32_t len, int32_t* out) {
+  int32_t a = S->rp[v], ae = S->rp[v + 1], b = 0, o = 0;
+  while (a < ae && S->col[a] <= v) a++;
+  while (a < ae && b < len) {
+    int32_t x = S->col[a], y = cand[b];
+    if (x == y) { out[o++] = x; a++; b++; }
+    else if (x < y) a++;
+    else b++;
+  }
+  return o;
+}
+
+/* Counts cliques R + (l vertices from cand) whose vertices ascend by id. */
+static uint64_t idrec(idrec_t* S, int32_t l, const int32_t* cand, int32_t len, int32_t depth) {
+  if (S->status) return 0;
+  if (l == 0) {
+    if (S->pv)
+      for (int32_t i = 0; i < depth; ++i) S->pv[S->R[i]]++;
+    return 1;
+  }
+  if (l == 1) {
+    if (S->pv) {
+      for (int32_t i = 0; i < depth; ++i) S->pv[S->R[i]] += (uint64_t)len;
+      for (int32_t i = 0; i < len; ++i) S->pv[cand[i]]++;
+    }
+    return (uint64_t)len;
+  }
+  uint64_t total = 0;
+  int32_t* next = S->buf + (size_t)(depth + 1) * (size_t)S->stride;
+  for (int32_t i = 0; i < len; ++i) {
+    int32_t v = cand[i];
+    S->isects++;
+    if (S->budget && S->isects > S->budget) { S->status = ORC_EBUDGET; return 0; }
+    if (S->deadline > 0.0 && (S->isects & 0xffff) == 0 && mono_now() > S->deadline) {
+      S->status = ORC_EBUDGET;
+      return total;
+    }
+    int32_t m = isect_up(S, v, cand + i + 1, len - i - 1, next);
+    if (m < l - 1) continue;
+    S->R[depth] = v;
+    uint64_t sub = idrec(S, l - 1, next, m, depth + 1);
+    if (add_checked(&total, sub)) { S->status = ORC_EOVERFLOW; return 0; }
+  }
+  return total;
+}
+
+static int32_t max_degree(int32_t n, const int32_t* rp) {
+  int32_t d = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] - rp[v] > d) d = rp[v + 1] - rp[v];
+  return d;
+}
+
+/* Counts over roots in roots[0..nroots) (NULL: all vertices).  Cliques are
+ * attributed to their smallest vertex id.  With a deadline, the count covers
+ * only the cliques found before it expired and the status is ORC_EBUDGET;
+ * *roots_done reports how many roots were completed. */
+int orc_count_idorder_roots(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, const int32_t* roots,
+                            int32_t nroots, double seconds, uint64_t* count, uint64_t* pv, int32_t* roots_done) {
+  if (n < 0 || k < 1) return ORC_EINVAL;
+  if (pv)
+    for (int32_t v = 0; v < n; ++v) pv[v] = 0;
+  *count = 0;
+  if (roots_done) *roots_done = 0;
+  if (n == 0) return ORC_OK;
+  idrec_t S;
+  memset(&S, 0, sizeof(S));
+  S.rp = rp;
+  S.col = col;
+  S.pv = pv;
+  S.stride = max_degree(n, rp) + 1;
+  S.R = (int32_t*)malloc(sizeof(int32_t) * ((size_t)k + 1));
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
+  if (!S.R || !S.buf) { free(S.R); free(S.buf); return ORC_ENOMEM; }
+  S.deadline = seconds > 0.0 ? mono_now() + seconds : 0.0;
+  int32_t total_roots = roots ? nroots : n;
+  for (int32_t t = 0; t < total_roots && !S.status; ++t) {
+    int32_t u = roots ? roots[t] : t;
+    /* candidates: neighbours with larger id */
+    int32_t m = 0;
+    for (int32_t i = rp[u]; i < rp[u + 1]; ++i)
+      if (col[i] > u) S.buf[m++] = col[i];
+    S.R[0] = u;
+    uint64_t sub = idrec(&S, k - 1, S.buf, m, 1);
+    if (add_checked(count, sub)) S.status = ORC_EOVERFLOW;
+    if (!S.status && roots_done) (*roots_done)++;
+  }
+  free(S.R);
+  free(S.buf);
+  return S.status;
+}
+
+int orc_count_idorder(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, uint64_t* count, uint64_t* pv) {
+  return orc_count_idorder_roots(n, rp, col, k, NULL, 0, 0.0, count, pv, NULL);
+}
+
+/* Participation of vertex v: (k-1)-cliques inside G[N(v)].  `budget` caps the
+ * number of intersections (0 = unlimited); ORC_EBUDGET when exceeded. */
+int orc_vertex_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, int32_t v, uint64_t budget,
+                     uint64_t* out) {
+  if (n < 0 || k < 1 || v < 0 || v >= n) return ORC_EINVAL;
+  *out = 0;
+  if (k == 1) { *out = 1; return ORC_OK; }
+  idrec_t S;
+  memset(&S, 0, sizeof(S));
+  S.rp = rp;
+  S.col = col;
+  S.budget = budget;
+  S.stride = max_degree(n, rp) + 1;
+  S.R = (int32_t*)malloc(sizeof(int32_t) * ((size_t)k + 2));
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 3));
+  if (!S.R || !S.buf) { free(S.R); free(S.buf); return ORC_ENOMEM; }
+  int32_t m = rp[v + 1] - rp[v];
+  memcpy(S.buf, col + rp[v], sizeof(int32_t) * (size_t)m);
+  /* (k-1)-cliques of G[N(v)]: the ordered recursion restricted to N(v) */
+  uint64_t total = idrec(&S, k - 1, S.buf, m, 0);
+  int st = S.status;
+  free(S.R);
+  free(S.buf);
+  if (st) return st;
+  *out = total;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------- core numbers */
+int orc_core_numbers(int32_t n, const int32_t* rp, const int32_t* col, int32_t* core) {
+  if (n < 0) return ORC_EINVAL;
+  if (n == 0) return ORC_OK;
+  int32_t md = max_degree(n, rp);
+  int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* bin = (int32_t*)calloc((size_t)md + 2, sizeof(int32_t));
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* vert = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!deg || !bin || !pos || !vert) { free(deg); free(bin); free(pos); free(vert); return ORC_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) { deg[v] = rp[v + 1] - rp[v]; bin[deg[v]]++; }
+  int32_t start = 0;
+  for (int32_t d = 0; d <= md; ++d) { int32_t c = bin[d]; bin[d] = start; start += c; }
+  for (int32_t v = 0; v < n; ++v) { pos[v] = bin[deg[v]]; vert[pos[v]] = v; bin[deg[v]]++; }
+  for (int32_t d = md; d >= 1; --d) bin[d] = bin[d - 1];
+  bin[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t v = vert[i];
+    for (int32_t j = rp[v]; j < rp[v + 1]; ++j) {
+      int32_t u = col[j];
+      if (deg[u] > deg[v]) {
+        int32_t du = deg[u], pu = pos[u], pw = bin[du], w = vert[pw];
+        if (u != w) { pos[u] = pw; vert[pu] = w; pos[w] = pu; vert[pw] = u; }
+        bin[du]++;
+        deg[u]--;
+      }
+    }
+  }
+  memcpy(core, deg, sizeof(int32_t) * (size_t)n);
+  free(deg); free(bin); free(pos); free(vert);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------ Pre-Core */
+/* removed[v] = 1 for every vertex Alg. 3 eliminates (degree < k-1 cascade). */
+int orc_precore(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, uint8_t* removed) {
+  if (n < 0 || k < 1) return ORC_EINVAL;
+  if (n == 0) return ORC_OK;
+  int32_t* d = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* Q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!d || !Q) { free(d); free(Q); return ORC_ENOMEM; }
+  int32_t head = 0, tail = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    d[u] = rp[u + 1] - rp[u];
+    removed[u] = 0;
+    if (d[u] < k - 1) { Q[tail++] = u; removed[u] = 1; }
+  }
+  while (head < tail) {
+    int32_t u = Q[head++];
+    for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+      int32_t v = col[i];
+      d[v]--;
+      if (d[v] < k - 1 && !removed[v]) { removed[v] = 1; Q[tail++] = v; }
+    }
+  }
+  free(d);
+  free(Q);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------ Pre-List */
+/* On the graph without `removed` vertices: every connected component whose
+ * degree sum is n_c(n_c-1) is a clique; its C(n_c,k) cliques are added to
+ * *count, C(n_c-1,k-1) to pv of each member (if pv), and it is marked in
+ * removed.  *n_cliques_out receives the number of such components. */
+int orc_prelist(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, uint8_t* removed, uint64_t* count,
+                uint64_t* pv, int32_t* n_clique_comps) {
+  if (n < 0 || k < 1) return ORC_EINVAL;
+  *count = 0;
+  if (n_clique_comps) *n_clique_comps = 0;
+  if (n == 0) return ORC_OK;
+  int32_t* comp = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* Q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!comp || !Q) { free(comp); free(Q); return ORC_ENOMEM; }
+  for (int32_t v = 0; v < n; ++v) comp[v] = -1;
+  int st = ORC_OK;
+  for (int32_t s = 0; s < n && !st; ++s) {
+    if (removed[s] || comp[s] >= 0) continue;
+    /* BFS */
+    int32_t head = 0, tail = 0;
+    Q[tail++] = s;
+    comp[s] = s;
+    int64_t degsum = 0;
+    while (head < tail) {
+      int32_t u = Q[head++];
+      for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+        int32_t v = col[i];
+        if (removed[v]) continue;
+        degsum++;
+        if (comp[v] < 0) { comp[v] = s; Q[tail++] = v; }
+      }
+    }
+    int64_t nc = tail;
+    if (degsum == nc * (nc - 1)) {
+      uint64_t c, cv = 0;
+      if (orc_binom((uint64_t)nc, (uint64_t)k, &c)) { st = ORC_EOVERFLOW; break; }
+      if (pv && orc_binom((uint64_t)nc - 1, (uint64_t)k - 1, &cv)) { st = ORC_EOVERFLOW; break; }
+      if (add_checked(count, c)) { st = ORC_EOVERFLOW; break; }
+      for (int32_t i = 0; i < tail; ++i) {
+        removed[Q[i]] = 1;
+        if (pv) pv[Q[i]] += cv;
+      }
+      if (n_clique_comps) (*n_clique_comps)++;
+    }
+  }
+  free(comp);
+  free(Q);
+  return st;
+}
+
+/* -------------------------------------------------------- orientations */
+/* Builds the out-neighbour lists of the live graph (removed[v] == 0) under a
+ * total order given by key[] (ties by id): u -> v iff (key_u,u) < (key_v,v).
+ * out_rp[n+1], out_col[<= nnz/2]; lists keep ascending id order. */
+static void build_dag(int32_t n, const int32_t* rp, const int32_t* col, const uint8_t* removed, const int64_t* key,
+                      int32_t* out_rp, int32_t* out_col) {
+  int32_t o = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    out_rp[u] = o;
+    if (removed[u]) continue;
+    for (int32_t i = rp[u]; i < rp[u + 1]; ++i) {
+      int32_t v = col[i];
+      if (removed[v]) continue;
+      if (key[u] < key[v] || (key[u] == key[v] && u < v)) out_col[o++] = v;
+    }
+  }
+  out_rp[n] = o;
+}
+
+int orc_degree_dag(int32_t n, const int32_t* rp, const int32_t* col, const uint8_t* removed, int32_t* out_rp,
+                   int32_t* out_col) {
+  if (n < 0) return ORC_EINVAL;
+  int64_t* key = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  if (!key) return ORC_ENOMEM;
+  for (int32_t u = 0; u < n; ++u) {
+    int64_t d = 0;
+    if (!removed[u])
+      for (int32_t i = rp[u]; i < rp[u + 1]; ++i) d += !removed[col[i]];
+    key[u] = d;
+  }
+  build_dag(n, rp, col, removed, key, out_rp, out_col);
+  free(key);
+  return ORC_OK;
+}
+
+/* Synchronous peel; round[v] and core[v] for live vertices (-1 if removed). */
+int orc_degeneracy_dag(int32_t n, const int32_t* rp, const int32_t* col, const uint8_t* removed, int32_t* out_rp,
+                       int32_t* out_col, int32_t* round_out, int32_t* core_out) {
+  if (n < 0) return ORC_EINVAL;
+  int64_t* key = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t* d = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  uint8_t* alive = (uint8_t*)malloc((size_t)n + 1);
+  int32_t* F = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  if (!key || !d || !alive || !F) { free(key); free(d); free(alive); free(F); return ORC_ENOMEM; }
+  int32_t live = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    alive[u] = !removed[u];
+    d[u] = 0;
+    key[u] = -1;
+    if (core_out) core_out[u] = -1;
+    if (!alive[u]) continue;
+    live++;
+    for (int32_t i = rp[u]; i < rp[u + 1]; ++i) d[u] += !removed[col[i]];
+  }
+  int32_t c = 0, round = 0;
+  while (live > 0) {
+    int32_t f = 0;
+    for (int32_t u = 0; u < n; ++u)
+      if (alive[u] && d[u] <= c) F[f++] = u;
+    if (f == 0) { c++; continue; }
+    for (int32_t i = 0; i < f; ++i) {
+      int32_t u = F[i];
+      key[u] = round;
+      if (core_out) core_out[u] = c;
+      alive[u] = 0;
+    }
+    for (int32_t i = 0; i < f; ++i) {
+      int32_t u = F[i];
+      for (int32_t j = rp[u]; j < rp[u + 1]; ++j)
+        if (alive[col[j]]) d[col[j]]--;
+    }
+    live -= f;
+    round++;
+  }
+  build_dag(n, rp, col, removed, key, out_rp, out_col);
+  if (round_out)
+    for (int32_t u = 0; u < n; ++u) round_out[u] = (int32_t)key[u];
+  free(key); free(d); free(alive); free(F);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------ SDegree, Alg. 5 */
+typedef struct {
+  const int32_t* drp; /* DAG */
+  const int32_t* dcol;
+  int32_t stride;
+  int32_t* buf;
+  uint64_t count, nodes, isect, elems;
+  int status;
+} sdeg_t;
+
+static int32_t merge_join(const int32_t* a, int32_t na, const int32_t* b, int32_t nb, int32_t* out) {
+  int32_t i = 0, j = 0, o = 0;
+  while (i < na && j < nb) {
+    if (a[i] == b[j]) { out[o++] = a[i]; i++; j++; }
+    else if (a[i] < b[j]) i++;
+    else j++;
+  }
+  return o;
+}
+
+/* exported for the worked-example test of the merge join (Sec. 6.3) */
+int32_t orc_merge_join(const int32_t* a, int32_t na, const int32_t* b, int32_t nb, int32_t* out) {
+  return merge_join(a, na, b, nb, out);
+}
+
+static void sdegree_list(sdeg_t* S, int32_t l, const int32_t* C, int32_t nc, int32_t depth) {
+  S->nodes++;
+  int32_t* next = S->buf + (size_t)(depth + 1) * (size_t)S->stride;
+  for (int32_t i = 0; i < nc && !S->status; ++i) {
+    int32_t u = C[i];
+    int32_t du = S->drp[u + 1] - S->drp[u];
+    if (du <= l - 2) continue;
+    int32_t m = merge_join(S->dcol + S->drp[u], du, C, nc, next);
+    S->isect++;
+    S->elems += (uint64_t)nc + (uint64_t)du;
+    if (l == 2) {
+      if (add_checked(&S->count, (uint64_t)m)) S->status = ORC_EOVERFLOW;
+    } else if (m > l - 2) {
+      sdegree_list(S, l - 1, next, m, depth + 1);
+    }
+  }
+}
+
+/* SDegree on a DAG.  Per root u (index = vertex id) the arrays receive the
+ * cliques found from u and the work counters (any may be NULL).  k >= 3. */
+int orc_sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, uint64_t* count,
+                    uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
+  if (n < 0 || k < 3) return ORC_EINVAL;
+  *count = 0;
+  int32_t md = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (drp[u + 1] - drp[u] > md) md = drp[u + 1] - drp[u];
+  sdeg_t S;
+  memset(&S, 0, sizeof(S));
+  S.drp = drp;
+  S.dcol = dcol;
+  S.stride = md + 1;
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
+  if (!S.buf) return ORC_ENOMEM;
+  for (int32_t u = 0; u < n && !S.status; ++u) {
+    int32_t du = drp[u + 1] - drp[u];
+    uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, e0 = S.elems;
+    if (du >= k - 1) {
+      memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
+      sdegree_list(&S, k - 1, S.buf, du, 0);
+    }
+    if (root_count) root_count[u] = S.count - c0;
+    if (root_nodes) root_nodes[u] = S.nodes - n0;
+    if (root_isect) root_isect[u] = S.isect - i0;
+    if (root_elems) root_elems[u] = S.elems - e0;
+  }
+  free(S.buf);
+  if (S.status) return S.status;
+  *count = S.count;
+  return ORC_OK;
+}
+
+/* ----------------------------------------------------- greedy coloring */
+/* Local graph on s vertices given by a dense 0/1 matrix adj[s*s] and their
+ * global ids.  order_out[i] = local index colored i-th; color_out[v] >= 1. */
+int orc_greedy_color(int32_t s, const uint8_t* adj, const int32_t* ids, int32_t* order_out, int32_t* color_out) {
+  if (s < 0) return ORC_EINVAL;
+  if (s == 0) return ORC_OK;
+  int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)s);
+  uint8_t* used = (uint8_t*)malloc((size_t)s + 2);
+  if (!deg || !used) { free(deg); free(used); return ORC_ENOMEM; }
+  for (int32_t v = 0; v < s; ++v) {
+    deg[v] = 0;
+    for (int32_t w = 0; w < s; ++w) deg[v] += adj[(size_t)v * s + w] ? 1 : 0;
+    order_out[v] = v;
+  }
+  /* insertion sort: degree descending, then id ascending */
+  for (int32_t i = 1; i < s; ++i) {
+    int32_t x = order_out[i], j = i - 1;
+    while (j >= 0) {
+      int32_t y = order_out[j];
+      int before = deg[x] > deg[y] || (deg[x] == deg[y] && ids[x] < ids[y]);
+      if (!before) break;
+      order_out[j + 1] = y;
+      --j;
+    }
+    order_out[j + 1] = x;
+  }
+  for (int32_t v = 0; v < s; ++v) color_out[v] = 0;
+  for (int32_t i = 0; i < s; ++i) {
+    int32_t v = order_out[i];
+    memset(used, 0, (size_t)s + 2);
+    for (int32_t w = 0; w < s; ++w)
+      if (adj[(size_t)v * s + w] && color_out[w] > 0 && color_out[w] <= s) used[color_out[w]] = 1;
+    int32_t c = 1;
+    while (used[c]) c++;
+    color_out[v] = c;
+  }
+  free(deg);
+  free(used);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------- BitCol, Alg. 6 */
+typedef struct {
+  int32_t s, L, nw;      /* local size, bits per word, words per bitmap */
+  const uint32_t* B;     /* s bitmaps of nw words */
+  const int32_t* color;  /* per local vertex */
+  uint32_t* stack;       /* candidate bitmaps, one per depth */
+  uint64_t count, nodes, isect, words;
+  int status;
+} bitcol_t;
+
+static int32_t bits_set(const uint32_t* x, int32_t nw) {
+  int32_t c = 0;
+  for (int32_t i = 0; i < nw; ++i) c += __builtin_popcount(x[i]);
+  return c;
+}
+
+static void bitcol_list(bitcol_t* S, int32_t l, const uint32_t* CB, int32_t depth) {
+  S->nodes++;
+  uint32_t* next = S->stack + (size_t)(depth + 1) * (size_t)S->nw;
+  for (int32_t v = 0; v < S->s && !S->status; ++v) {
+    /* decode: v is a member of CB */
+    if (!((CB[v / S->L] >> (v % S->L)) & 1u)) continue;
+    if (S->color[v] < l) continue;
+    const uint32_t* Bv = S->B + (size_t)v * S->nw;
+    for (int32_t i = 0; i < S->nw; ++i) next[i] = Bv[i] & CB[i]; /* BitJoin */
+    S->isect++;
+    S->words += (uint64_t)((S->s + 31) / 32);
+    int32_t p = bits_set(next, S->nw);
+    if (l == 2) {
+      if (add_checked(&S->count, (uint64_t)p)) S->status = ORC_EOVERFLOW;
+    } else if (p >= l - 1) {
+      bitcol_list(S, l - 1, next, depth + 1);
+    }
+  }
+}
+
+/* Encodes one local graph: colors and bitmaps B (s x ceil(s/L) words, L <= 32)
+ * of the color-ordered DAG.  ids[] are the global ids (tie-break). */
+int orc_bitcol_encode(int32_t s, const uint8_t* adj, const int32_t* ids, int32_t L, int32_t* color,
+                      uint32_t* B) {
+  if (s < 0 || L < 1 || L > 32) return ORC_EINVAL;
+  if (s == 0) return ORC_OK;
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)s);
+  if (!order) return ORC_ENOMEM;
+  int st = orc_greedy_color(s, adj, ids, order, color);
+  free(order);
+  if (st) return st;
+  int32_t nw = (s + L - 1) / L;
+  memset(B, 0, sizeof(uint32_t) * (size_t)s * (size_t)nw);
+  for (int32_t v = 0; v < s; ++v)
+    for (int32_t w = 0; w < s; ++w)
+      if (adj[(size_t)v * s + w] && color[w] < color[v]) B[(size_t)v * nw + w / L] |= 1u << (w % L);
+  return ORC_OK;
+}
+
+/* BitCol on a DAG (normally the degeneracy DAG).  Per root u: cliques found,
+ * work counters, and the features d+_u, number of colors of G_u, |E_u|. */
+int orc_bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, uint64_t* count,
+                   uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_words,
+                   int32_t* root_colors, int64_t* root_edges) {
+  if (n < 0 || k < 3 || L < 1 || L > 32) return ORC_EINVAL;
+  *count = 0;
+  int32_t md = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (drp[u + 1] - drp[u] > md) md = drp[u + 1] - drp[u];
+  int32_t nwmax = (md + L - 1) / L + 1;
+  uint8_t* adj = (uint8_t*)malloc((size_t)md * (size_t)md + 1);
+  int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * ((size_t)md + 1));
+  int32_t* color = (int32_t*)malloc(sizeof(int32_t) * ((size_t)md + 1));
+  uint32_t* B = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)md + 1) * (size_t)nwmax);
+  uint32_t* stack = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nwmax * ((size_t)k + 2));
+  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  if (!adj || !ids || !color || !B || !stack || !pos) {
+    free(adj); free(ids); free(color); free(B); free(stack); free(pos);
+    return ORC_ENOMEM;
+  }
+  for (int32_t v = 0; v < n; ++v) pos[v] = -1;
+  bitcol_t S;
+  memset(&S, 0, sizeof(S));
+  S.L = L;
+  S.stack = stack;
+  int st = ORC_OK;
+  for (int32_t u = 0; u < n && !st; ++u) {
+    int32_t s = drp[u + 1] - drp[u];
+    if (root_count) root_count[u] = 0;
+    if (root_nodes) root_nodes[u] = 0;
+    if (root_isect) root_isect[u] = 0;
+    if (root_words) root_words[u] = 0;
+    if (root_colors) root_colors[u] = 0;
+    if (root_edges) root_edges[u] = 0;
+    if (s < k - 1) continue;
+    /* G_u: induced by N+(u), local index = position in N+(u) */
+    for (int32_t i = 0; i < s; ++i) { ids[i] = dcol[drp[u] + i]; pos[ids[i]] = i; }
+    memset(adj, 0, (size_t)s * (size_t)s);
+    int64_t ecount = 0;
+    for (int32_t i = 0; i < s; ++i) {
+      int32_t v = ids[i];
+      for (int32_t j = drp[v]; j < drp[v + 1]; ++j) {
+        int32_t w = dcol[j];
+        if (pos[w] >= 0) {
+          adj[(size_t)i * s + pos[w]] = 1;
+          adj[(size_t)pos[w] * s + i] = 1;
+          ecount++;
+        }
+      }
+    }
+    for (int32_t i = 0; i < s; ++i) pos[ids[i]] = -1;
+    st = orc_bitcol_encode(s, adj, ids, L, color, B);
+    if (st) break;
+    int32_t ncolors = 0;
+    for (int32_t i = 0; i < s; ++i) ncolors = color[i] > ncolors ? color[i] : ncolors;
+    S.s = s;
+    S.nw = (s + L - 1) / L;
+    S.B = B;
+    S.color = color;
+    uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, w0 = S.words;
+    /* top call: C_B = every local vertex (B_u(u)) */
+    for (int32_t i = 0; i < S.nw; ++i) stack[i] = 0;
+    for (int32_t i = 0; i < s; ++i) stack[i / L] |= 1u << (i % L);
+    bitcol_list(&S, k - 1, stack, 0);
+    st = S.status;
+    if (root_count) root_count[u] = S.count - c0;
+    if (root_nodes) root_nodes[u] = S.nodes - n0;
+    if (root_isect) root_isect[u] = S.isect - i0;
+    if (root_words) root_words[u] = S.words - w0;
+    if (root_colors) root_colors[u] = ncolors;
+    if (root_edges) root_edges[u] = ecount;
+  }
+  free(adj); free(ids); free(color); free(B); free(stack); free(pos);
+  if (st) return st;
+  *count = S.count;
+  return ORC_OK;
+}
+
+/* ------------------------------------------- whole methods (Alg. 5, 6) */
+/* Pre-Core, Pre-List, orientation and listing, as the paper orders them.
+ * method 0 = SDegree (degree DAG), 1 = BitCol (degeneracy DAG, L bits).
+ * Returns the total count (Pre-List cliques included); the per-root arrays
+ * (size n, may be NULL) describe the listing phase only. */
+int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, int32_t method, int32_t L,
+                     uint64_t* count, uint64_t* prelist_count, uint64_t* root_count, uint64_t* root_nodes,
+                     uint64_t* root_isect, uint64_t* root_work, int32_t* root_dplus, int32_t* root_core,
+                     int32_t* root_colors, int64_t* root_edges) {
+  if (n < 0 || k < 3) return ORC_EINVAL;
+  *count = 0;
+  if (prelist_count) *prelist_count = 0;
+  if (n == 0) return ORC_OK;
+  uint8_t* removed = (uint8_t*)malloc((size_t)n);
+  int32_t* drp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t* dcol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)rp[n] / 2 + 1));
+  int32_t* core = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!removed || !drp || !dcol || !core) { free(removed); free(drp); free(dcol); free(core); return ORC_ENOMEM; }
+  int st = orc_precore(n, rp, col, k, removed);
+  uint64_t pl = 0;
+  if (!st) st = orc_prelist(n, rp, col, k, removed, &pl, NULL, NULL);
+  if (!st) {
+    if (method == 0) st = orc_degree_dag(n, rp, col, removed, drp, dcol);
+    else st = orc_degeneracy_dag(n, rp, col, removed, drp, dcol, NULL, core);
+  }
+  uint64_t c = 0;
+  if (!st) {
+    if (method == 0) st = orc_sdegree_dag(n, drp, dcol, k, &c, root_count, root_nodes, root_isect, root_work);
+    else st = orc_bitcol_dag(n, drp, dcol, k, L, &c, root_count, root_nodes, root_isect, root_work, root_colors,
+                             root_edges);
+  }
+  if (!st) {
+    if (root_dplus)
+      for (int32_t u = 0; u < n; ++u) root_dplus[u] = drp[u + 1] - drp[u];
+    if (root_core && method == 1) memcpy(root_core, core, sizeof(int32_t) * (size_t)n);
+    if (add_checked(&c, pl)) st = ORC_EOVERFLOW;
+  }
+  if (!st) {
+    *count = c;
+    if (prelist_count) *prelist_count = pl;
+  }
+  free(removed); free(drp); free(dcol); free(core);
+  return st;
+}
