@@ -1,0 +1,155 @@
+/*
+ * kclique.h -- exact k-clique counting on one AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the k-clique listing method of "Efficient k-clique
+ * Listing with Set Intersection Speedup" (Yuan et al.): Pre-Core and Pre-List
+ * preprocessing (Sec. 5, Alg. 3 and Alg. 4), an acyclic orientation by degree
+ * (SDegree, Sec. 6, Alg. 5) or by degeneracy with a per-root greedy color
+ * ordering and bitmap intersections (BitCol, Sec. 7, Alg. 6), and a recursive
+ * listing whose last level is counted.  Every result is an exact unsigned
+ * 64-bit integer; no rounding is involved.
+ *
+ * Graph input (every entry point): a simple undirected graph in CSR form.
+ *   n         number of vertices (0 <= n < 2^31)
+ *   row_ptr   int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] < 2^31
+ *   col_idx   int32[row_ptr[n]], the neighbours of v are
+ *             col_idx[row_ptr[v] .. row_ptr[v+1]), strictly ascending, in
+ *             [0, n), never v itself; the graph is symmetric (w in N(v) iff
+ *             v in N(w)).  Every undirected edge therefore appears twice.
+ * Unless the options mark the input trusted, the library checks all of this
+ * on the device and returns KC_EINVAL on any violation.
+ *
+ * k: k >= 1.  k = 1 gives n, k = 2 gives the number of edges, k > n gives 0.
+ * (The paper treats k >= 3; the two linear cases follow Sec. 8.)
+ *
+ * Ownership: the caller owns every buffer.  The library keeps no pointer after
+ * returning and allocates its scratch memory on the device for the duration
+ * of a call (stream-ordered), freeing it before returning.  Calls that share a
+ * stream are serialised by it; calls on different streams are independent.
+ *
+ * Errors: every function returns a kc_status.  On a non-zero status the
+ * outputs are unspecified.  No C++ exception crosses this interface.
+ */
+#ifndef KCLIQUE_H
+#define KCLIQUE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KC_OK = 0,
+  KC_EINVAL = -1,        /* malformed graph, k < 1, unknown order/schedule */
+  KC_ENOMEM = -2,        /* device allocation failed */
+  KC_EOVERFLOW = -3,     /* a count does not fit in 64 bits (e.g. C(201,20)) */
+  KC_EDEVICE = -4,       /* a HIP runtime call failed or no device */
+  KC_EUNSUPPORTED = -5   /* a local subgraph exceeds the supported size */
+} kc_status;
+
+/* Orientation / algorithm. */
+#define KC_ORDER_DEGREE 0 /* SDegree: degree order, sorted-list merge joins (Alg. 5) */
+#define KC_ORDER_COLOR 1  /* BitCol: degeneracy order + per-root color order, bitmaps (Alg. 6) */
+
+/* Root schedule of the persistent listing kernel (does not change results). */
+#define KC_SCHED_DEGREE 0  /* roots ordered and split by DAG out-degree */
+#define KC_SCHED_LEARNED 1 /* roots ordered and split by the MLP's predicted work */
+
+/* Number of floats in an MLP parameter block (see kc_mlp_* below). */
+#define KC_MLP_IN 4
+#define KC_MLP_HIDDEN 64
+#define KC_MLP_NPARAMS (KC_MLP_IN * KC_MLP_HIDDEN + KC_MLP_HIDDEN + KC_MLP_HIDDEN * KC_MLP_HIDDEN + KC_MLP_HIDDEN + KC_MLP_HIDDEN + 1)
+
+/* Timings and counters of the last call (filled when kc_options.stats is set). */
+typedef struct {
+  double total_ms;        /* device time of the whole call (events on its stream) */
+  double prep_ms;         /* validation, Pre-Core, Pre-List, orientation */
+  double stage_ms;        /* BitCol: local subgraph staging, coloring, encoding */
+  double sched_ms;        /* features, MLP inference, binning, task generation */
+  double list_ms;         /* the persistent listing kernel(s) */
+  int32_t list_launches;  /* listing kernel launches in the call */
+  int32_t n_roots;        /* roots with d+ >= k-1 */
+  int64_t n_tasks;        /* work items in the queue(s) */
+  int32_t max_out_degree; /* largest d+ among roots */
+  int32_t max_core;       /* degeneracy (COLOR order only) */
+  uint64_t prelist_count; /* cliques reported by Pre-List */
+  uint64_t nodes;         /* calls of the listing procedure */
+  uint64_t isect;         /* set intersections (merge joins or BitJoins) */
+  uint64_t work;          /* SDegree: sum of |C|+d+ per join; BitCol: sum of ceil(s/32) words per BitJoin */
+  uint64_t staged_words;  /* BitCol: 32-bit words of encoded bitmaps written */
+  uint64_t stage_bytes;   /* BitCol: algorithmic bytes read while staging: 4*(d+_u + sum of d+_v) */
+} kc_stats;
+
+typedef struct {
+  int32_t device_ptrs;    /* 1: row_ptr, col_idx and every output are device pointers */
+  void* stream;           /* hipStream_t; NULL = the default stream */
+  int32_t trusted_input;  /* 1: skip the O(m log d) CSR validation */
+  int32_t schedule;       /* KC_SCHED_DEGREE (default) or KC_SCHED_LEARNED */
+  const float* mlp_params;/* LEARNED: device pointer, KC_MLP_NPARAMS floats */
+  const float* mlp_norm;  /* LEARNED: device pointer, 8 floats: feature mean[4], std[4] (of log1p features) */
+  int32_t waves_per_root; /* BitCol waves sharing one root's bitmaps: 0 = auto, else 1, 2 or 4 */
+  int32_t chunk;          /* tasks taken per queue access: 0 = auto */
+  int32_t split;          /* heavy-root splitting: 0 = auto, -1 = never, 1/2 = force that depth for heavy roots */
+  float split_threshold;  /* 0 = auto: schedule key above which roots are split */
+  /* optional per-vertex logs, device pointers of n entries (NULL = off):
+   * the root's listing work (as kc_stats.work) and its features */
+  uint64_t* root_work;
+  uint64_t* root_isect;
+  float* root_features;   /* n x 4: d+_u, core(u), colors of G_u, |E_u| (BitCol only) */
+  kc_stats* stats;        /* host pointer or NULL */
+} kc_options;
+
+/* Zero-filled options = defaults. */
+void kc_options_init(kc_options* opt);
+
+/* Number of k-cliques (Sec. 3.1: all k-cliques of G).  row_ptr, col_idx and
+ * count_out are host pointers.  order: KC_ORDER_DEGREE or KC_ORDER_COLOR. */
+int kclique_count(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                  uint64_t* count_out);
+
+/* Per-vertex participation: per_vertex_out[v] = number of k-cliques that
+ * contain v (host array of n entries); count_out (nullable) = total.  The
+ * per-vertex values sum to k times the total. */
+int kclique_list_per_vertex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                            uint64_t* per_vertex_out, uint64_t* count_out);
+
+/* Full form of both calls.  per_vertex_out may be NULL (count only).  With
+ * opt->device_ptrs the graph and outputs live in device memory. */
+int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                     const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out);
+
+/* Many independent graphs in one call: graph g has n[g] vertices, its rows
+ * start at row_ptr_cat[row_off[g]] (n[g]+1 entries, local offsets starting at
+ * 0) and its columns at col_idx_cat[col_off[g]] (local vertex ids).  k[g] per
+ * graph.  counts_out[g] receives graph g's count.  Pointers follow
+ * opt->device_ptrs for the concatenated arrays and counts_out; n, row_off,
+ * col_off and k are always host arrays. */
+int kclique_count_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off, const int64_t* col_off,
+                          const int32_t* row_ptr_cat, const int32_t* col_idx_cat, const int32_t* k, int32_t order,
+                          const kc_options* opt, uint64_t* counts_out);
+
+/* ---- learned scheduling: MLP 4 -> 64 -> 64 -> 1, ReLU, FP32 -------------
+ * Parameter block layout (KC_MLP_NPARAMS floats, row-major):
+ *   W1[64][4], b1[64], W2[64][64], b2[64], W3[64] (1 x 64), b3[1].
+ * y = W3 relu(W2 relu(W1 x + b1) + b2) + b3.  All pointers are device
+ * pointers; calls are ordered on `stream` (NULL = default stream). */
+
+/* y[i] = MLP(x[i]) for i < rows; x is rows x 4 (row-major). */
+int kc_mlp_forward(const float* params, const float* x, int32_t rows, float* y, void* stream);
+
+/* One training step on a minibatch: mean squared error between MLP(x) and
+ * target; grad (KC_MLP_NPARAMS) receives d loss / d params, loss_out (one
+ * float, device) the loss.  Then, if lr > 0, one Adam step (Kingma and Ba)
+ * with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 updates params in place using
+ * the moment buffers m, v (KC_MLP_NPARAMS each) and the 1-based step t. */
+int kc_mlp_train_step(float* params, const float* x, const float* target, int32_t rows, float* grad, float* loss_out,
+                      float* m, float* v, int32_t t, float lr, void* stream);
+
+const char* kc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KCLIQUE_H */

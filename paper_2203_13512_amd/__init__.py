@@ -1,0 +1,268 @@
+"""Exact k-clique counting on an AMD Instinct MI355X (gfx950).
+
+Thin binding over the C interface in ``include/kclique.h`` (library
+``libkclique.so`` next to this file).  Arguments are marshalled into the C
+calls; every step of the computation runs in the library's HIP kernels.  The
+binding refuses to run when the library is missing -- there is no fallback.
+
+Graph arguments are int32 CSR arrays (symmetric, rows sorted, no loops):
+either torch tensors on the GPU (used in place, on torch's current stream) or
+numpy arrays on the host (copied by the library).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkclique.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "kclique.h")
+
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+ORDERS = {"degree": 0, "color": 1}
+SCHEDULES = {"degree": 0, "learned": 1}
+MLP_IN, MLP_HIDDEN = 4, 64
+MLP_NPARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+
+
+class KCliqueError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _lib().kc_status_string(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("stage_ms", ctypes.c_double),
+        ("sched_ms", ctypes.c_double), ("list_ms", ctypes.c_double), ("list_launches", ctypes.c_int32),
+        ("n_roots", ctypes.c_int32), ("n_tasks", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
+        ("max_core", ctypes.c_int32), ("prelist_count", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
+        ("isect", ctypes.c_uint64), ("work", ctypes.c_uint64), ("staged_words", ctypes.c_uint64),
+        ("stage_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("device_ptrs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("trusted_input", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("mlp_params", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p),
+        ("waves_per_root", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
+        ("split_threshold", ctypes.c_float), ("root_work", ctypes.c_void_p), ("root_isect", ctypes.c_void_p),
+        ("root_features", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats)),
+    ]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_13512_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)
+    L.kc_status_string.restype = ctypes.c_char_p
+    L.kc_status_string.argtypes = [ctypes.c_int]
+    L.kclique_count.restype = ctypes.c_int
+    L.kclique_count.argtypes = [i32, vp, vp, i32, i32, u64p]
+    L.kclique_list_per_vertex.restype = ctypes.c_int
+    L.kclique_list_per_vertex.argtypes = [i32, vp, vp, i32, i32, vp, u64p]
+    L.kclique_count_ex.restype = ctypes.c_int
+    L.kclique_count_ex.argtypes = [i32, vp, vp, i32, i32, ctypes.POINTER(Options), u64p, vp]
+    L.kclique_count_batched.restype = ctypes.c_int
+    L.kclique_count_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp]
+    L.kc_mlp_forward.restype = ctypes.c_int
+    L.kc_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.kc_mlp_train_step.restype = ctypes.c_int
+    L.kc_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.kc_options_init.restype = None
+    L.kc_options_init.argtypes = [ctypes.POINTER(Options)]
+    _LIB = L
+    return L
+
+
+def declared_symbols(header: str = HEADER) -> list[str]:
+    """Function names declared in the public header."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(k[c\w]*)\s*\(", text)) - {"kc_status"})
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _torch_stream(dev):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise KCliqueError(st, what)
+
+
+def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False, schedule: str = "degree",
+          mlp=None, trusted: bool = False, waves_per_root: int = 0, chunk: int = 0, split: int = 0,
+          split_threshold: float = 0.0, root_logs: bool = False, stats: bool = False):
+    """Number of k-cliques (and per-vertex participation).
+
+    Returns ``count`` or, with ``per_vertex``, ``(count, pv)`` where pv[v]
+    is the number of k-cliques containing v (int64 values, torch tensor on the
+    GPU for GPU input, numpy array otherwise).  With ``stats`` a dict of the
+    call's timings and work counters is appended; with ``root_logs`` (GPU
+    input only) the per-vertex root logs (work, joins, features) are added to
+    that dict.
+    """
+    L = _lib()
+    opt = Options()
+    L.kc_options_init(ctypes.byref(opt))
+    st = Stats()
+    opt.stats = ctypes.pointer(st)
+    opt.trusted_input = 1 if trusted else 0
+    opt.schedule = SCHEDULES[schedule]
+    opt.waves_per_root = waves_per_root
+    opt.chunk = chunk
+    opt.split = split
+    opt.split_threshold = split_threshold
+    out = ctypes.c_uint64(0)
+    keep = []
+    on_gpu = _is_torch(row_ptr) and row_ptr.is_cuda
+    if on_gpu:
+        import torch
+        rp = row_ptr.contiguous()
+        ci = col_idx.contiguous()
+        if rp.dtype != torch.int32 or ci.dtype != torch.int32:
+            raise TypeError("row_ptr and col_idx must be int32")
+        n = rp.numel() - 1
+        dev = rp.device
+        opt.device_ptrs = 1
+        opt.stream = _torch_stream(dev)
+        pv = torch.zeros(max(n, 1), dtype=torch.int64, device=dev) if per_vertex else None
+        logs = None
+        if root_logs:
+            logs = dict(work=torch.zeros(max(n, 1), dtype=torch.int64, device=dev),
+                        isect=torch.zeros(max(n, 1), dtype=torch.int64, device=dev),
+                        features=torch.zeros((max(n, 1), 4), dtype=torch.float32, device=dev))
+            opt.root_work = logs["work"].data_ptr()
+            opt.root_isect = logs["isect"].data_ptr()
+            opt.root_features = logs["features"].data_ptr()
+        if schedule == "learned":
+            if mlp is None:
+                raise ValueError("the learned schedule needs mlp=(params, norm) device tensors")
+            params, norm = mlp
+            opt.mlp_params = params.data_ptr()
+            opt.mlp_norm = norm.data_ptr()
+            keep += [params, norm]
+        rc = L.kclique_count_ex(n, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k, ORDERS[order],
+                                ctypes.byref(opt), ctypes.byref(out), pv.data_ptr() if pv is not None else None)
+        _check(rc, "kclique_count_ex")
+        res = [int(out.value)]
+        if per_vertex:
+            res.append(pv[:n])
+        if stats or root_logs:
+            d = st.as_dict()
+            if logs is not None:
+                d["root_logs"] = {key: v[:n] for key, v in logs.items()}
+            res.append(d)
+    else:
+        if root_logs or schedule == "learned":
+            raise ValueError("root logs and the learned schedule take GPU tensors")
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        n = len(rp) - 1
+        pv = np.zeros(max(n, 1), dtype=np.uint64) if per_vertex else None
+        rc = L.kclique_count_ex(n, rp.ctypes.data, ci.ctypes.data if ci.size else None, k, ORDERS[order],
+                                ctypes.byref(opt), ctypes.byref(out), pv.ctypes.data if pv is not None else None)
+        _check(rc, "kclique_count_ex")
+        res = [int(out.value)]
+        if per_vertex:
+            res.append(pv[:n].astype(np.int64))
+        if stats:
+            res.append(st.as_dict())
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def count_host(row_ptr, col_idx, k: int, order: str = "color") -> int:
+    """The plain ``kclique_count`` entry point (host arrays)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    out = ctypes.c_uint64(0)
+    _check(_lib().kclique_count(len(rp) - 1, rp.ctypes.data, ci.ctypes.data if ci.size else None, k, ORDERS[order],
+                                ctypes.byref(out)), "kclique_count")
+    return int(out.value)
+
+
+def per_vertex_host(row_ptr, col_idx, k: int, order: str = "color"):
+    """The plain ``kclique_list_per_vertex`` entry point (host arrays)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = len(rp) - 1
+    pv = np.zeros(max(n, 1), dtype=np.uint64)
+    out = ctypes.c_uint64(0)
+    _check(_lib().kclique_list_per_vertex(n, rp.ctypes.data, ci.ctypes.data if ci.size else None, k, ORDERS[order],
+                                          pv.ctypes.data, ctypes.byref(out)), "kclique_list_per_vertex")
+    return int(out.value), pv[:n]
+
+
+def count_batched(graphs, ks, order: str = "color", **kw):
+    """Counts of many graphs in one call; graphs are (row_ptr, col_idx) host
+    arrays.  Returns a list of counts."""
+    L = _lib()
+    ns = np.asarray([len(g[0]) - 1 for g in graphs], dtype=np.int32)
+    roff = np.zeros(len(graphs), dtype=np.int64)
+    coff = np.zeros(len(graphs), dtype=np.int64)
+    r_acc = c_acc = 0
+    for i, (rp, ci) in enumerate(graphs):
+        roff[i], coff[i] = r_acc, c_acc
+        r_acc += len(rp)
+        c_acc += len(ci)
+    rp_cat = np.ascontiguousarray(np.concatenate([np.asarray(g[0], np.int32) for g in graphs]) if graphs
+                                  else np.zeros(1, np.int32))
+    ci_cat = np.ascontiguousarray(np.concatenate([np.asarray(g[1], np.int32) for g in graphs] + [np.zeros(1, np.int32)]))
+    kk = np.ascontiguousarray(ks, dtype=np.int32)
+    out = np.zeros(max(len(graphs), 1), dtype=np.uint64)
+    opt = Options()
+    L.kc_options_init(ctypes.byref(opt))
+    for key, v in kw.items():
+        setattr(opt, key, v)
+    rc = L.kclique_count_batched(len(graphs), ns.ctypes.data, roff.ctypes.data, coff.ctypes.data, rp_cat.ctypes.data,
+                                 ci_cat.ctypes.data, kk.ctypes.data, ORDERS[order], ctypes.byref(opt),
+                                 out.ctypes.data)
+    _check(rc, "kclique_count_batched")
+    return [int(x) for x in out[:len(graphs)]]
+
+
+# ------------------------------------------------------------------ MLP
+def mlp_forward(params, x):
+    """y = MLP(x) for x of shape (rows, 4); GPU tensors (float32)."""
+    import torch
+    rows = x.shape[0]
+    y = torch.empty(rows, dtype=torch.float32, device=x.device)
+    _check(_lib().kc_mlp_forward(params.data_ptr(), x.contiguous().data_ptr(), rows, y.data_ptr(),
+                                 _torch_stream(x.device)), "kc_mlp_forward")
+    return y
+
+
+def mlp_train_step(params, x, target, m=None, v=None, t: int = 1, lr: float = 0.0):
+    """One minibatch step; returns (loss tensor[1], grad tensor).  With lr > 0
+    the parameters are updated in place by Adam using moments m, v."""
+    import torch
+    rows = x.shape[0]
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(_lib().kc_mlp_train_step(params.data_ptr(), x.contiguous().data_ptr(), target.contiguous().data_ptr(),
+                                    rows, grad.data_ptr(), loss.data_ptr(),
+                                    m.data_ptr() if m is not None else None, v.data_ptr() if v is not None else None,
+                                    t, lr, _torch_stream(x.device)), "kc_mlp_train_step")
+    return loss, grad

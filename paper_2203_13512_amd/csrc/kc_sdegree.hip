@@ -1,0 +1,327 @@
+// kc_sdegree.hip -- SDegree (Alg. 5, Sec. 6.2) on gfx950.
+//
+// One wave per root u with d+_u >= k-1 (NodeParallel, Sec. 9).  The candidate
+// set C of every recursion level is a sorted list of vertex ids held in LDS
+// (or, for very large out-degrees, in a per-workgroup slice of device
+// memory).  The merge join of Alg. 5 -- C' = N+(x) intersected with C -- is
+// done with 64 lanes at a time: the lanes load 64 consecutive entries of the
+// sorted list N+(x) (one coalesced load), each lane looks its entry up in C by
+// binary search, and a ballot compacts the hits into the next level's list
+// in order (mbcnt gives each hit its slot).  The part of N+(x) below min(C)
+// is skipped with one binary search and the scan stops past max(C), so a
+// join touches only the range where matches can occur.  At l = 2 the hits
+// are only counted.  Pruning follows Alg. 5: x is skipped when d+_x <= l-2,
+// and a child list is entered only when it holds more than l-2 members.
+// Work is logged as |C| + d+_x per join, the cost term of Lemma 2.
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "kc_internal.h"
+
+#define SD_NCLASS 6
+static const int kSClass[SD_NCLASS] = {64, 256, 1024, 4096, 16384, 65536};
+
+__device__ __forceinline__ int sd_class_of(int s) {
+  if (s <= 64) return 0;
+  if (s <= 256) return 1;
+  if (s <= 1024) return 2;
+  if (s <= 4096) return 3;
+  if (s <= 16384) return 4;
+  if (s <= 65536) return 5;
+  return -1;
+}
+
+struct SdArgs {
+  const int32_t* drp;
+  const int32_t* dcol;
+  const int32_t* roots;
+  const int32_t* tasks;  // root indices in schedule order
+  int32_t ntasks;
+  unsigned long long* head;
+  int chunk;
+  int k;
+  int SMAX;
+  uint32_t* gscratch;     // per-workgroup memory when the lists do not fit LDS
+  size_t block_words;
+  unsigned long long* count;
+  unsigned long long* pv;
+  unsigned long long* counters;
+  uint64_t* root_work;
+  uint64_t* root_isect;
+  int* flags;
+};
+
+// Memory of one workgroup (words): list[K][SMAX] | lidx[K][SMAX] (per-vertex)
+// | cnt[SMAX] u64 (per-vertex) | cur[K] | size[K] | chosen[K] | tot[K] u64
+static size_t sd_words(int k, int smax, bool pv) {
+  size_t K = (size_t)k;
+  return K * smax * (pv ? 2 : 1) + (pv ? 2 * (size_t)smax : 0) + 5 * K + 8;
+}
+
+__device__ __forceinline__ int sd_lower_bound(const int32_t* a, int lo, int hi, int32_t x) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <bool PV>
+__global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
+  extern __shared__ uint32_t lds[];
+  uint32_t* mem = a.gscratch ? a.gscratch + (size_t)blockIdx.x * a.block_words : lds;
+  const int K = a.k;
+  const int SM = a.SMAX;
+  int32_t* list = (int32_t*)mem;
+  int32_t* lidx = list + (size_t)K * SM;
+  unsigned long long* cnt = (unsigned long long*)(lidx + (PV ? (size_t)K * SM : 0));
+  int32_t* cur = (int32_t*)(cnt + (PV ? SM : 0));
+  int32_t* size = cur + K;
+  int32_t* chosen = size + K;
+  unsigned long long* tot = (unsigned long long*)(((uintptr_t)(chosen + K) + 7) & ~(uintptr_t)7);
+  const int lane = threadIdx.x;
+  __shared__ int32_t sh_task[2];
+
+  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;
+  for (;;) {
+    if (lane == 0) {
+      unsigned long long t = atomicAdd(a.head, (unsigned long long)a.chunk);
+      sh_task[0] = (int32_t)(t < (unsigned long long)a.ntasks ? t : a.ntasks);
+      long long e = (long long)t + a.chunk;
+      sh_task[1] = (int32_t)(e < a.ntasks ? e : a.ntasks);
+    }
+    __syncthreads();
+    const int32_t t_lo = sh_task[0], t_hi = sh_task[1];
+    __syncthreads();
+    if (t_lo >= t_hi) break;
+    for (int32_t ti = t_lo; ti < t_hi; ++ti) {
+      const int32_t r = a.tasks[ti];
+      const int32_t u = a.roots[r];
+      const int32_t b0 = a.drp[u];
+      const int32_t s0 = a.drp[u + 1] - b0;
+      for (int i = lane; i < s0; i += 64) {
+        list[i] = a.dcol[b0 + i];
+        if (PV) {
+          lidx[i] = i;
+          cnt[i] = 0;
+        }
+      }
+      if (lane == 0) {
+        cur[0] = 0;
+        size[0] = s0;
+        tot[0] = 0;
+      }
+      __syncthreads();
+      my_nodes++;
+      const int L0 = K - 1;
+      int d = 0;
+      for (;;) {
+        const int l = L0 - d;
+        const int sz = size[d];
+        const int c = cur[d];
+        if (c >= sz) {
+          if (d == 0) break;
+          unsigned long long T = tot[d];
+          if (lane == 0) {
+            tot[d - 1] += T;
+            if (PV && T) atomicAdd(&cnt[chosen[d - 1]], T);
+          }
+          kc_wave_lds_sync();
+          d--;
+          continue;
+        }
+        int32_t* C = list + (size_t)d * SM;
+        const int32_t x = C[c];
+        const int xi = PV ? lidx[(size_t)d * SM + c] : 0;
+        if (lane == 0) cur[d] = c + 1;
+        kc_wave_lds_sync();
+        const int32_t xb = a.drp[x], xe = a.drp[x + 1];
+        const int dx = xe - xb;
+        if (dx <= l - 2) continue;
+        my_isect++;
+        my_work += (uint64_t)sz + (uint64_t)dx;
+        // merge join N+(x) with C
+        const int32_t cmin = C[0], cmax = C[sz - 1];
+        // first entry of N+(x) that can match
+        int start;
+        {
+          int lo = xb, hi = xe;
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (a.dcol[mid] < cmin) lo = mid + 1; else hi = mid;
+          }
+          start = lo;
+        }
+        int32_t* Cn = list + (size_t)(d + 1) * SM;
+        int32_t* Ln = lidx + (size_t)(d + 1) * SM;
+        int m = 0;
+        int lo_pos = 0;
+        for (int i0 = start; i0 < xe; i0 += 64) {
+          const int i = i0 + lane;
+          const int32_t y = i < xe ? a.dcol[i] : 0x7fffffff;
+          const int32_t yfirst = __shfl(y, 0, 64);
+          if (yfirst > cmax) break;
+          int p = -1;
+          if (y <= cmax) {
+            int q = sd_lower_bound(C, lo_pos, sz, y);
+            if (q < sz && C[q] == y) p = q;
+          }
+          const bool hit = p >= 0;
+          const uint64_t mk = kc_ballot(hit);
+          if (l == 2) {
+            if (PV && hit) atomicAdd(&cnt[lidx[(size_t)d * SM + p]], 1ull);
+          } else if (hit) {
+            const int o = m + kc_mbcnt(mk);
+            Cn[o] = y;
+            if (PV) Ln[o] = lidx[(size_t)d * SM + p];
+          }
+          m += __popcll(mk);
+          // entries of the next chunk are larger than every entry here
+          const int32_t ylast = __shfl(y, 63, 64);
+          if (ylast > cmax) break;
+          lo_pos = sd_lower_bound(C, lo_pos, sz, ylast);
+        }
+        if (l == 2) {
+          if (lane == 0) {
+            tot[d] += (unsigned long long)m;
+            if (PV && m) atomicAdd(&cnt[xi], (unsigned long long)m);
+          }
+          kc_wave_lds_sync();
+        } else if (m > l - 2) {
+          if (lane == 0) {
+            chosen[d] = xi;
+            size[d + 1] = m;
+            cur[d + 1] = 0;
+            tot[d + 1] = 0;
+          }
+          kc_wave_lds_sync();
+          d++;
+          my_nodes++;
+        }
+      }
+      __syncthreads();
+      const unsigned long long T = tot[0];
+      if (lane == 0 && T) {
+        kc_add_checked(a.count, T, a.flags);
+        if (PV) kc_add_checked(&a.pv[u], T, a.flags);
+      }
+      if (PV)
+        for (int i = lane; i < s0; i += 64) {
+          unsigned long long cc = cnt[i];
+          if (cc) kc_add_checked(&a.pv[a.dcol[b0 + i]], cc, a.flags);
+        }
+      if (lane == 0) {
+        if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)my_isect);
+        if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)my_work);
+        atomicAdd(&a.counters[0], (unsigned long long)my_nodes);
+        atomicAdd(&a.counters[1], (unsigned long long)my_isect);
+        atomicAdd(&a.counters[2], (unsigned long long)my_work);
+      }
+      my_nodes = my_isect = my_work = 0;
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp, int k,
+                          int32_t* bin, int* flags) {
+  int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int32_t u = roots[r];
+  int s = drp[u + 1] - drp[u];
+  int c = sd_class_of(s);
+  if (c < 0) {
+    atomicOr(flags, KC_FLAG_TOOBIG);
+    c = 0;
+  }
+  // degree schedule: larger d+ first inside a class
+  float lw = lgammaf((float)s + 1.f) - lgammaf((float)k) - lgammaf((float)(s - k + 2));
+  bin[r] = c * 64 + 63 - kc_key_q(lw);
+}
+
+int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
+  const int32_t R = c.nroots;
+  if (R == 0) return KC_OK;
+  const bool pv = c.pv != nullptr;
+  int32_t *bin, *order;
+  KC_TRY(scr.get(&bin, R));
+  KC_TRY(scr.get(&order, R));
+  k_sd_bins<<<(R + 255) / 256, 256, 0, st>>>(R, c.roots, c.drp, c.k, bin, c.flags);
+  KC_HIP(hipGetLastError());
+  const int NB = SD_NCLASS * 64;
+  std::vector<int32_t> boff(NB + 1);
+  KC_TRY(kc_bin_sort(bin, R, NB, order, boff.data(), scr, st));
+  int hflags = 0;
+  KC_HIP(hipMemcpyAsync(&hflags, c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
+  unsigned long long* heads;
+  KC_TRY(scr.get(&heads, SD_NCLASS));
+  KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * SD_NCLASS, st));
+  hipEvent_t e0, e1;
+  KC_HIP(hipEventCreate(&e0));
+  KC_HIP(hipEventCreate(&e1));
+  KC_HIP(hipEventRecord(e0, st));
+  int launches = 0;
+  for (int cl = SD_NCLASS - 1; cl >= 0; --cl) {
+    int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
+    if (hi <= lo) continue;
+    SdArgs a;
+    a.drp = c.drp;
+    a.dcol = c.dcol;
+    a.roots = c.roots;
+    a.tasks = order + lo;
+    a.ntasks = hi - lo;
+    a.head = heads + cl;
+    a.chunk = c.opt && c.opt->chunk > 0 ? c.opt->chunk : (cl <= 1 ? 8 : 1);
+    a.k = c.k;
+    a.SMAX = kSClass[cl];
+    a.count = c.count;
+    a.pv = c.pv;
+    a.counters = c.counters;
+    a.root_work = c.root_work;
+    a.root_isect = c.root_isect;
+    a.flags = c.flags;
+    size_t words = sd_words(c.k, a.SMAX, pv);
+    size_t bytes = 4 * words;
+    auto fn = pv ? k_sdegree_list<true> : k_sdegree_list<false>;
+    int64_t grid;
+    size_t lds_bytes;
+    if (bytes <= 64 * 1024) {
+      a.gscratch = nullptr;
+      a.block_words = 0;
+      lds_bytes = bytes;
+      KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+      int per_cu = 0;
+      KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds_bytes));
+      grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * kc_device_cus();
+    } else {
+      grid = (int64_t)kc_device_cus() * 8;
+      if (grid > a.ntasks) grid = a.ntasks;
+      a.block_words = (words + 63) & ~(size_t)63;
+      KC_TRY(scr.get(&a.gscratch, a.block_words * (size_t)grid));
+      lds_bytes = 0;
+    }
+    if (grid > a.ntasks) grid = a.ntasks;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds_bytes, st, a);
+    KC_HIP(hipGetLastError());
+    launches++;
+  }
+  KC_HIP(hipEventRecord(e1, st));
+  if (c.stats) {
+    float ms = 0.f;
+    KC_HIP(hipEventSynchronize(e1));
+    KC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    c.stats->list_ms += ms;
+    c.stats->list_launches += launches;
+    c.stats->n_tasks += R;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return KC_OK;
+}

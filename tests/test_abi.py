@@ -1,0 +1,45 @@
+"""The C interface: the library builds for gfx950, loads, and exports every
+function the public header declares (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+import paper_2203_13512_amd as kc
+
+
+def test_header_declares_the_boundary():
+    names = kc.declared_symbols()
+    for f in ["kclique_count", "kclique_list_per_vertex", "kclique_count_ex", "kclique_count_batched",
+              "kc_mlp_forward", "kc_mlp_train_step", "kc_status_string", "kc_options_init"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(kc.LIB_PATH), "build the library first (__graft_entry__.build())"
+    lib = ctypes.CDLL(kc.LIB_PATH)
+    for name in kc.declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_without_device():
+    lib = kc._lib()
+    for st in (0, -1, -2, -3, -4, -5):
+        assert lib.kc_status_string(st)
+
+
+def test_struct_layouts_match_header():
+    # sizes fixed by the header's field order on x86-64
+    assert ctypes.sizeof(kc.Stats) == 5 * 8 + 2 * 4 + 8 + 2 * 4 + 6 * 8
+    assert kc.Options.stats.offset == ctypes.sizeof(kc.Options) - 8
+
+
+def test_mlp_param_count():
+    assert kc.MLP_NPARAMS == 4 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def test_binding_refuses_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(kc, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(kc, "_LIB", None)
+    with pytest.raises(RuntimeError):
+        kc._lib()
