@@ -1,0 +1,163 @@
+"""Benchmark: exact k-clique counting on one MI355X.
+
+Workload (default): Chung-Lu power-law graph, n = 4,000,000, mean degree 30,
+exponent 2.0, max weight sqrt(n * mean degree), with 8 planted cliques
+(201, 160, 128, 100, 80, 64, 50, 40 vertices); k = 8; BitCol (color order).
+A step is one whole call of the library on the graph already resident in HBM:
+validation, Pre-Core, Pre-List, degeneracy orientation, staging/coloring/
+encoding, features + MLP inference + binning + task generation, and the
+persistent listing kernels.  The learned schedule (MLP trained on per-root
+work logged from the smaller workloads) and the degree schedule run the same
+kernels; both counts must equal each other.
+
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts used for the roofline
+MI355X_CUS = 256
+MI355X_CLOCK_HZ = 2.4e9
+# int32 VALU: 4 SIMDs x 16 lanes per CU per clock (v_and_b32, v_bcnt_u32_b32)
+INT32_VALU_PEAK_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_HZ / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=5, help="1, 2, 3 or 5 (see graphgen.workload)")
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--order", default="color")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--schedules", default="learned,degree")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2203_13512_amd as kc
+    from paper_2203_13512_amd import scheduler
+
+    t0 = time.time()
+    w = graphgen.workload(args.workload, scale=args.scale)
+    rp_h, ci_h = w.graphs[0]
+    k = args.k or {1: 4, 2: 7, 3: 8, 5: 8}[args.workload]
+    log(f"workload {w.name}: n={len(rp_h) - 1} nnz={len(ci_h)} k={k} generated in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(rp_h).to(dev)
+    ci = torch.from_numpy(ci_h).to(dev)
+    torch.cuda.synchronize()
+
+    schedules = [s for s in args.schedules.split(",") if s]
+    mlp = None
+    if "learned" in schedules:
+        mlp = scheduler.load_model(dev, k)
+        if mlp is None:
+            log("no trained scheduler model found; running the degree schedule only")
+            schedules = [s for s in schedules if s != "learned"]
+
+    results = {}
+    for sched in schedules:
+        kw = dict(schedule=sched, stats=True)
+        if sched == "learned":
+            kw["mlp"] = mlp
+        for i in range(args.warmup):
+            c, st = kc.count(rp, ci, k, args.order, **kw)
+            torch.cuda.synchronize()
+            log(f"[{sched}] warmup {i}: count={c} total={st['total_ms']:.1f}ms list={st['list_ms']:.1f}ms")
+        times, lists, counts, stats = [], [], [], []
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            c, st = kc.count(rp, ci, k, args.order, **kw)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - ts
+            times.append(el)
+            lists.append(st["list_ms"])
+            counts.append(c)
+            stats.append(st)
+            log(f"[{sched}] step {i}: count={c} wall={el * 1e3:.1f}ms device={st['total_ms']:.1f}ms "
+                f"prep={st['prep_ms']:.1f} stage={st['stage_ms']:.1f} sched={st['sched_ms']:.1f} "
+                f"list={st['list_ms']:.1f} tasks={st['n_tasks']}")
+        assert len(set(counts)) == 1, counts
+        results[sched] = dict(count=counts[0], step_s=sum(times) / len(times),
+                              list_ms=sum(lists) / len(lists), stats=stats[-1])
+    counts = {s: r["count"] for s, r in results.items()}
+    assert len(set(counts.values())) == 1, f"schedules disagree: {counts}"
+    main_sched = "learned" if "learned" in results else schedules[0]
+    R = results[main_sched]
+    cnt = R["count"]
+    value = cnt / R["step_s"]
+    st = R["stats"]
+    # roofline of the dominant kernel (the persistent BitCol listing kernel):
+    # algorithmic work = ceil(s/32) words per BitJoin, AND + popcount = 2 int ops per word
+    list_s = R["list_ms"] / 1e3
+    alg_ops = 2.0 * st["work"]
+    achieved = alg_ops / list_s / 1e12 if list_s > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT32_VALU_PEAK_TOPS, 3),
+                "unit": "TOP/s", "frac": round(achieved / INT32_VALU_PEAK_TOPS, 5), "traffic": None,
+                "kernel": "k_bitcol_list (all word classes)", "list_ms": round(R["list_ms"], 3),
+                "algorithmic_words": st["work"], "bitjoins": st["isect"]}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(7)
+        roots = rng.permutation(len(rp_h) - 1).astype(np.int32)
+        t = time.perf_counter()
+        c_cpu, done, finished = oracle.count_roots(rp_h, ci_h, k, roots, seconds=args.cpu_seconds)
+        el = time.perf_counter() - t
+        cpu = {"value": c_cpu / el, "unit": "k-cliques/s", "cores": 1, "kind": "oracle",
+               "sample": f"ordered-recursion oracle (single thread) over roots in a fixed random order for "
+                         f"{args.cpu_seconds:.0f}s: {done} roots completed, {c_cpu} cliques counted in {el:.1f}s"}
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "k-cliques/sec on 1 MI355X: learned-scheduled vs degree-scheduled, exact count",
+        "value": value,
+        "unit": "k-cliques/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["step_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} k={k} {args.order} order", "k": k, "order": args.order,
+                   "schedule": main_sched, "n": int(len(rp_h) - 1), "nnz": int(len(ci_h)), "count": cnt},
+        "schedules": {s: {"value": r["count"] / r["step_s"], "ms_per_step": r["step_s"] * 1e3,
+                          "list_ms": r["list_ms"], "n_tasks": r["stats"]["n_tasks"]} for s, r in results.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "learned" in results and "degree" in results:
+        out["learned_speedup_vs_degree"] = results["degree"]["step_s"] / results["learned"]["step_s"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

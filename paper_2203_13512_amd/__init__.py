@@ -42,11 +42,16 @@ class Stats(ctypes.Structure):
         ("n_roots", ctypes.c_int32), ("n_tasks", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
         ("max_core", ctypes.c_int32), ("prelist_count", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
         ("isect", ctypes.c_uint64), ("work", ctypes.c_uint64), ("staged_words", ctypes.c_uint64),
-        ("stage_bytes", ctypes.c_uint64),
+        ("stage_bytes", ctypes.c_uint64), ("class_ms", ctypes.c_double * 8), ("class_work", ctypes.c_uint64 * 8),
+        ("class_tasks", ctypes.c_int64 * 8),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
 
 
 class Options(ctypes.Structure):

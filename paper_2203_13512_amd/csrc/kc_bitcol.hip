@@ -328,7 +328,7 @@ struct ListArgs {
 //   B[W][S+1] | Bin[W][S+1] (per-vertex) | color[S] | firstpos[KMAX+2] |
 //   C0[W] | shared scalars[16] | NW wave blocks | cnt[S] u64 (per-vertex)
 // A wave block holds tot[KMAX+1] u64 | cur[KMAX+1] | chosen[KMAX+1] |
-// stack[(KMAX+1)][W].
+// stack[(KMAX+1)][W] | candidate lists[2][S] u16 | pairs[2S] u32.
 #define KC_KMAX 32
 
 template <int W, int NW, bool PV>
@@ -343,7 +343,8 @@ struct ListLayout {
   static constexpr int oC0 = oFirst + KC_KMAX + 2;
   static constexpr int oSh = a2(oC0 + W);
   static constexpr int oWave = oSh + 16;
-  static constexpr int wave_words = a2(4 * (KC_KMAX + 1) + (KC_KMAX + 1) * W);
+  static constexpr int PCAP = 2 * S;  // (x, v) pairs buffered per wave
+  static constexpr int wave_words = a2(4 * (KC_KMAX + 1) + (KC_KMAX + 1) * W + S / 2 + S / 2 + PCAP);
   static constexpr int oCnt = oWave + NW * wave_words;
   static constexpr int words = oCnt + (PV ? 2 * S : 0);
   static constexpr size_t bytes() { return 4 * (size_t)words; }
@@ -415,6 +416,232 @@ __device__ __forceinline__ uint64_t leaf_eval(const uint32_t* __restrict__ Bl, c
   return (uint64_t)kc_wave_sum_u32(total);
 }
 
+// Level-3 node with set C (lane-split word in `cw`), evaluated lane-parallel:
+// the members v of C with color >= 3 are compacted into `vlist` and dealt to
+// lanes (passes part, part+nparts, ... of 64); each lane forms C' = B(v) & C
+// in registers and, when |C'| >= 2, walks the members w of C' with color >= 2
+// itself, adding popcount(B(w) & C') (B(w) only has bits below w, so only the
+// words up to w's own word are read).  This is BitColList at l = 3 and l = 2
+// with the same pruning and join count, without wave-wide steps per node.
+// Returns this lane's share of the node's leaves; joins/nodes are per lane.
+template <int W, bool PV>
+__device__ __forceinline__ uint64_t level3_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
+                                                int s, int first2, int first3, uint32_t cw, int lane,
+                                                uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes,
+                                                unsigned long long* cnt, int part, int nparts) {
+  constexpr int SP = 32 * W + 1;
+  const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
+  if (hiw < 0) return 0;
+  uint32_t c[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) c[i] = kc_readlane(cw, i);
+  const int end = (hiw + 1) * 32 < s ? (hiw + 1) * 32 : s;
+  int mcount = 0;
+  for (int p0 = first3 & ~63; p0 < end; p0 += 64) {
+    const int p = p0 + lane;
+    const uint32_t word = (uint32_t)__shfl((int)cw, (p >> 5) & 63, 64);
+    const bool mem = p >= first3 && p < end && ((word >> (p & 31)) & 1u);
+    const uint64_t mk = kc_ballot(mem);
+    if (mem) vlist[mcount + kc_mbcnt(mk)] = (uint16_t)p;
+    mcount += __popcll(mk);
+  }
+  kc_wave_lds_sync();
+  const int f2w = first2 >> 5;
+  const uint32_t f2m = (~0u) << (first2 & 31);
+  uint64_t total = 0;
+  for (int base = part * 64; base < mcount; base += 64 * nparts) {
+    const int idx = base + lane;
+    if (idx >= mcount) continue;
+    const int v = vlist[idx];
+    joins++;
+    uint32_t cv[W];
+    int pc = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      cv[i] = i <= hiw ? (Bl[i * SP + v] & c[i]) : 0u;
+      pc += __popc(cv[i]);
+    }
+    if (pc < 2) continue;
+    nodes++;
+    uint32_t leaf = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      uint32_t m = cv[i];
+      if (!PV) m = i < f2w ? 0u : (i == f2w ? (m & f2m) : m);
+      while (m) {
+        const int b = __ffs(m) - 1;
+        m &= m - 1;
+        const int w = i * 32 + b;
+        uint32_t out = 0;
+        if (!PV || w >= first2) {
+#pragma unroll
+          for (int j = 0; j <= i; ++j) out += (uint32_t)__popc(Bl[j * SP + w] & cv[j]);
+          joins++;
+        }
+        leaf += out;
+        if (PV) {
+          uint32_t in = 0;
+#pragma unroll
+          for (int j = i; j < W; ++j) in += (uint32_t)__popc(Bil[j * SP + w] & cv[j]);
+          if (out + in) atomicAdd(&cnt[w], (unsigned long long)(out + in));
+        }
+      }
+    }
+    total += leaf;
+    if (PV && leaf) atomicAdd(&cnt[v], (unsigned long long)leaf);
+  }
+  return total;
+}
+
+// Level-4 node with set C (lane-split `cw`), evaluated lane-parallel over
+// (x, v) pairs: lanes first take the members x of C with color >= 4, form
+// C3 = B(x) & C and count the members v of C3 with color >= 3; the pairs
+// (x, v) of the x with |C3| >= 3 are written to an LDS list and then dealt to
+// lanes, each forming C2 = B(v) & C3 and, when |C2| >= 2, counting the
+// leaves below it as level3_eval does.  Small level-3 nodes thus share
+// passes instead of each leaving most lanes idle.  When a batch of x yields
+// more pairs than the buffer holds (dense sets), its x are evaluated one by
+// one with level3_eval, which is efficient for large sets.
+template <int W, bool PV>
+__device__ __forceinline__ uint64_t level4_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
+                                                int s, int first2, int first3, int first4, uint32_t cw, int lane,
+                                                uint16_t* __restrict__ xlist, uint16_t* __restrict__ vlist,
+                                                uint32_t* __restrict__ pairs, int pcap, uint64_t& joins,
+                                                uint64_t& nodes, unsigned long long* cnt, int part, int nparts) {
+  constexpr int SP = 32 * W + 1;
+  const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
+  if (hiw < 0) return 0;
+  uint32_t c[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) c[i] = kc_readlane(cw, i);
+  const int end = (hiw + 1) * 32 < s ? (hiw + 1) * 32 : s;
+  int mx = 0;
+  for (int p0 = first4 & ~63; p0 < end; p0 += 64) {
+    const int p = p0 + lane;
+    const uint32_t word = (uint32_t)__shfl((int)cw, (p >> 5) & 63, 64);
+    const bool mem = p >= first4 && p < end && ((word >> (p & 31)) & 1u);
+    const uint64_t mk = kc_ballot(mem);
+    if (mem) xlist[mx + kc_mbcnt(mk)] = (uint16_t)p;
+    mx += __popcll(mk);
+  }
+  kc_wave_lds_sync();
+  const int f2w = first2 >> 5, f3w = first3 >> 5;
+  const uint32_t f2m = (~0u) << (first2 & 31), f3m = (~0u) << (first3 & 31);
+  uint64_t total = 0;
+  for (int xb = part * 64; xb < mx; xb += 64 * nparts) {
+    const int idx = xb + lane;
+    const bool valid = idx < mx;
+    const int x = valid ? xlist[idx] : 0;
+    uint32_t c3[W];
+    int p3 = 0, nv = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      c3[i] = (valid && i <= hiw) ? (Bl[i * SP + x] & c[i]) : 0u;
+      p3 += __popc(c3[i]);
+      const uint32_t mv = i < f3w ? 0u : (i == f3w ? (c3[i] & f3m) : c3[i]);
+      nv += __popc(mv);
+    }
+    joins += valid ? 1 : 0;
+    const bool q = valid && p3 >= 3;
+    nodes += q ? 1 : 0;
+    if (!q) nv = 0;
+    // exclusive prefix of nv over the wave
+    int incl = nv;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int P = __shfl(incl, 63, 64);
+    const int off = incl - nv;
+    if (P == 0) continue;
+    if (P > pcap) {
+      // dense batch: one level-3 node at a time
+      uint64_t qm = kc_ballot(q);
+      while (qm) {
+        const int fl = __ffsll((long long)qm) - 1;
+        qm &= qm - 1;
+        const int xx = __shfl(x, fl, 64);
+        // lane i needs word i of lane fl's C3
+        uint32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          uint32_t wv = kc_readlane(c3[i], fl);
+          if (lane == i) mine = wv;
+        }
+        uint64_t t3 = level3_eval<W, PV>(Bl, Bil, s, first2, first3, mine, lane, vlist, joins, nodes, cnt, 0, 1);
+        total += t3;
+        if (PV) {
+          uint64_t T3 = kc_wave_sum_u64(t3);
+          if (lane == 0 && T3) atomicAdd(&cnt[xx], (unsigned long long)T3);
+        }
+      }
+      continue;
+    }
+    // write this lane's pairs
+    if (q) {
+      int j = off;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        uint32_t m = i < f3w ? 0u : (i == f3w ? (c3[i] & f3m) : c3[i]);
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          pairs[j++] = ((uint32_t)x << 16) | (uint32_t)(i * 32 + b);
+        }
+      }
+    }
+    kc_wave_lds_sync();
+    for (int pb = 0; pb < P; pb += 64) {
+      const int pi = pb + lane;
+      if (pi >= P) continue;
+      const uint32_t pr = pairs[pi];
+      const int px = (int)(pr >> 16), v = (int)(pr & 0xffff);
+      uint32_t c2[W];
+      int pc = 0;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        c2[i] = i <= hiw ? (Bl[i * SP + px] & c[i] & Bl[i * SP + v]) : 0u;
+        pc += __popc(c2[i]);
+      }
+      joins++;
+      if (pc < 2) continue;
+      nodes++;
+      uint32_t leaf = 0;
+#pragma unroll
+      for (int i = 0; i < W; ++i) {
+        uint32_t m = c2[i];
+        if (!PV) m = i < f2w ? 0u : (i == f2w ? (m & f2m) : m);
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          const int w = i * 32 + b;
+          uint32_t out = 0;
+          if (!PV || w >= first2) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) out += (uint32_t)__popc(Bl[j * SP + w] & c2[j]);
+            joins++;
+          }
+          leaf += out;
+          if (PV) {
+            uint32_t in = 0;
+#pragma unroll
+            for (int j = i; j < W; ++j) in += (uint32_t)__popc(Bil[j * SP + w] & c2[j]);
+            if (out + in) atomicAdd(&cnt[w], (unsigned long long)(out + in));
+          }
+        }
+      }
+      total += leaf;
+      if (PV && leaf) {
+        atomicAdd(&cnt[v], (unsigned long long)leaf);
+        atomicAdd(&cnt[px], (unsigned long long)leaf);
+      }
+    }
+    kc_wave_lds_sync();
+  }
+  return total;
+}
+
 template <int W, int NW, bool PV>
 __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   using LY = ListLayout<W, NW, PV>;
@@ -426,7 +653,7 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   uint32_t* col = lds + LY::oCol;
   int32_t* firstpos = (int32_t*)(lds + LY::oFirst);
   uint32_t* C0 = lds + LY::oC0;
-  int32_t* sh = (int32_t*)(lds + LY::oSh);  // [0] task lo, [1] task hi, [2] child cursor, [3] child limit
+  int32_t* sh = (int32_t*)(lds + LY::oSh);  // [0] task lo, [1] task hi, [2] child cursor
   unsigned long long* shtot = (unsigned long long*)(lds + LY::oSh + 8);
   unsigned long long* cnt = (unsigned long long*)(lds + LY::oCnt);
 
@@ -438,9 +665,12 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   int32_t* cur = (int32_t*)(wblk + 2 * (KC_KMAX + 1));
   int32_t* chosen = cur + (KC_KMAX + 1);
   uint32_t* stk = (uint32_t*)(chosen + (KC_KMAX + 1));
+  uint16_t* xlist = (uint16_t*)(stk + (KC_KMAX + 1) * W);
+  uint16_t* vlist = xlist + S;
+  uint32_t* pairs = (uint32_t*)(vlist + S);
 
   const int k = a.k;
-  uint64_t my_nodes = 0, my_isect = 0;
+  uint64_t my_nodes = 0, my_isect = 0;  // per lane
 
   for (;;) {
     if (tid == 0) {
@@ -502,23 +732,30 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       if (v1 >= 0) L0--;
       if (v2 >= 0) L0--;
       __syncthreads();
+      const int first2 = firstpos[2], first3 = firstpos[3];
       if (wid == 0) my_nodes += (lane == 0);
-      uint64_t wave_total = 0;
+      uint64_t wave_total = 0;  // per lane
       const uint32_t c0w = lane < W ? C0[lane] : 0u;
-      // positions past the highest member of C0 hold no children
-      int limit = 0;
-      {
-        int hiw = kc_wave_max_i32((lane < W && c0w) ? lane : -1);
-        if (hiw >= 0) limit = hiw * 32 + 32 - __clz((int)kc_readlane(c0w, hiw));
-      }
       if (L0 == 2) {
-        // the task node itself is a level-2 node: its 64-position chunks are
-        // dealt round-robin to the waves
+        // the task node is a level-2 node: its 64-position chunks are dealt
+        // round-robin to the waves
         uint64_t j = 0;
-        wave_total = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], c0w, lane, j, cnt, wid, NW);
+        uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, first2, c0w, lane, j, cnt, wid, NW);
+        wave_total += (lane == 0) ? t2 : 0;
         my_isect += (lane == 0) ? j : 0;
+      } else if (L0 == 3) {
+        wave_total += level3_eval<W, PV>(Bl, Bil, s, first2, first3, c0w, lane, vlist, my_isect, my_nodes, cnt, wid,
+                                         NW);
+      } else if (L0 == 4) {
+        wave_total += level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], c0w, lane, xlist, vlist, pairs,
+                                         LY::PCAP, my_isect, my_nodes, cnt, wid, NW);
       } else {
         // children of the task node are handed out to waves
+        int limit = 0;
+        {
+          int hiw = kc_wave_max_i32((lane < W && c0w) ? lane : -1);
+          if (hiw >= 0) limit = hiw * 32 + 32 - __clz((int)kc_readlane(c0w, hiw));
+        }
         for (;;) {
           int v = -1;
           if (lane == 0) {
@@ -531,78 +768,82 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
           v = __shfl(v, 0, 64);
           if (v < 0) break;
           // BitJoin at the task level
-          uint32_t cw = lane < W ? (Bl[lane * SP + v] & c0w) : 0u;
+          const uint32_t cw = lane < W ? (Bl[lane * SP + v] & c0w) : 0u;
           my_isect += (lane == 0);
-          uint32_t pc = split_popc(cw);
-          uint64_t sub = 0;
-          if ((int)pc >= L0 - 1) {
-            if (L0 - 1 == 2) {
-              uint64_t j = 0;
-              sub = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], cw, lane, j, cnt);
-              my_isect += (lane == 0) ? j : 0;
-              my_nodes += (lane == 0);
-            } else {
-              // depth-first from (L0-1, cw)
-              my_nodes += (lane == 0);
-              if (lane < W) stk[lane] = cw;
-              int d = 0;
-              if (lane == 0) { cur[0] = firstpos[L0 - 1]; tot[0] = 0; }
-              kc_wave_lds_sync();
-              for (;;) {
-                const int l = L0 - 1 - d;
-                const uint32_t mw = lane < W ? stk[d * W + lane] : 0u;
-                const int from = __shfl(cur[d], 0, 64);
-                const int x = split_next<W>(mw, from, lane);
-                if (x < 0) {
-                  if (d == 0) break;
-                  // finished child at depth d: credit its total upward
+          const uint32_t pc = split_popc(cw);
+          if ((int)pc < L0 - 1) continue;
+          my_nodes += (lane == 0);
+          uint64_t sub = 0;  // per lane share of the child's leaves
+          if (L0 - 1 == 4) {
+            sub = level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], cw, lane, xlist, vlist, pairs, LY::PCAP,
+                                     my_isect, my_nodes, cnt, 0, 1);
+          } else {
+            // depth-first from (L0-1, cw); nodes of level 4 are evaluated whole
+            if (lane < W) stk[lane] = cw;
+            int d = 0;
+            if (lane == 0) { cur[0] = firstpos[L0 - 1]; tot[0] = 0; }
+            kc_wave_lds_sync();
+            uint64_t lane_acc = 0;  // this lane's leaves below the child, credited per level
+            for (;;) {
+              const int l = L0 - 1 - d;
+              const uint32_t mw = lane < W ? stk[d * W + lane] : 0u;
+              const int from = cur[d];
+              const int x = split_next<W>(mw, from, lane);
+              if (x < 0) {
+                if (d == 0) break;
+                if (PV && lane == 0) {
                   unsigned long long T = tot[d];
+                  tot[d - 1] += T;
+                  if (T) atomicAdd(&cnt[chosen[d - 1]], T);
+                }
+                kc_wave_lds_sync();
+                d--;
+                continue;
+              }
+              if (lane == 0) cur[d] = x + 1;
+              kc_wave_lds_sync();
+              const uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
+              my_isect += (lane == 0);
+              const uint32_t npc = split_popc(nw);
+              if ((int)npc < l - 1) continue;
+              my_nodes += (lane == 0);
+              if (l - 1 == 4) {
+                uint64_t t3 = level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], nw, lane, xlist, vlist,
+                                                 pairs, LY::PCAP, my_isect, my_nodes, cnt, 0, 1);
+                lane_acc += t3;
+                if (PV) {
+                  // the node total is needed for the chosen vertices above
+                  uint64_t T3 = kc_wave_sum_u64(t3);
                   if (lane == 0) {
-                    tot[d - 1] += T;
-                    if (PV && T) atomicAdd(&cnt[chosen[d - 1]], T);
+                    tot[d] += T3;
+                    if (T3) atomicAdd(&cnt[x], (unsigned long long)T3);
                   }
                   kc_wave_lds_sync();
-                  d--;
-                  continue;
                 }
-                if (lane == 0) cur[d] = x + 1;
+              } else {
+                if (lane == 0) {
+                  chosen[d] = x;
+                  cur[d + 1] = firstpos[l - 1];
+                  tot[d + 1] = 0;
+                }
+                if (lane < W) stk[(d + 1) * W + lane] = nw;
                 kc_wave_lds_sync();
-                uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
-                my_isect += (lane == 0);
-                uint32_t npc = split_popc(nw);
-                if ((int)npc >= l - 1) {
-                  my_nodes += (lane == 0);
-                  if (l - 1 == 2) {
-                    uint64_t j = 0;
-                    uint64_t T2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], nw, lane, j, cnt);
-                    my_isect += (lane == 0) ? j : 0;
-                    if (lane == 0) {
-                      tot[d] += T2;
-                      if (PV && T2) atomicAdd(&cnt[x], (unsigned long long)T2);
-                    }
-                    kc_wave_lds_sync();
-                  } else {
-                    if (lane == 0) {
-                      chosen[d] = x;
-                      cur[d + 1] = firstpos[l - 1];
-                      tot[d + 1] = 0;
-                    }
-                    if (lane < W) stk[(d + 1) * W + lane] = nw;
-                    kc_wave_lds_sync();
-                    d++;
-                  }
-                }
+                d++;
               }
-              sub = tot[0];
             }
+            sub = lane_acc;
           }
-          if (lane == 0 && sub) {
-            wave_total += sub;
-            if (PV) atomicAdd(&cnt[v], (unsigned long long)sub);
+          if (PV) {
+            uint64_t T = kc_wave_sum_u64(sub);
+            if (lane == 0 && T) atomicAdd(&cnt[v], (unsigned long long)T);
           }
+          wave_total += sub;
         }
       }
-      if (lane == 0 && wave_total) atomicAdd(&shtot[0], (unsigned long long)wave_total);
+      {
+        const uint64_t wt = kc_wave_sum_u64(wave_total);
+        if (lane == 0 && wt) atomicAdd(&shtot[0], (unsigned long long)wt);
+      }
       __syncthreads();
       // task epilogue
       const uint64_t T = shtot[0];
@@ -621,18 +862,21 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
           if (c) kc_add_checked(&a.pv[a.perm[po + p]], c, a.flags);
         }
       }
-      __syncthreads();
       // per-root work log (flushed per task)
-      if (lane == 0 && (my_isect || my_nodes)) {
-        if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)my_isect);
-        if (a.root_work)
-          atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)my_isect * (uint64_t)((s + 31) / 32));
-        atomicAdd(&a.counters[0], (unsigned long long)my_nodes);
-        atomicAdd(&a.counters[1], (unsigned long long)my_isect);
-        atomicAdd(&a.counters[2], (unsigned long long)my_isect * (uint64_t)((s + 31) / 32));
+      {
+        const uint64_t wi = kc_wave_sum_u64(my_isect), wn = kc_wave_sum_u64(my_nodes);
+        if (lane == 0 && (wi || wn)) {
+          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+          if (a.root_work)
+            atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)wi * (uint64_t)((s + 31) / 32));
+          atomicAdd(&a.counters[0], (unsigned long long)wn);
+          atomicAdd(&a.counters[1], (unsigned long long)wi);
+          atomicAdd(&a.counters[2], (unsigned long long)wi * (uint64_t)((s + 31) / 32));
+        }
       }
       my_nodes = 0;
       my_isect = 0;
+      __syncthreads();
     }
   }
 }
@@ -848,6 +1092,15 @@ __global__ void k_scatter_features(int32_t R, const int32_t* __restrict__ roots,
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * 4) return;
   out[4 * (int64_t)roots[i >> 2] + (i & 3)] = f[i];
+}
+
+__global__ void k_add_counters(const unsigned long long* __restrict__ per_class, int ncls, unsigned long long* total) {
+  int i = threadIdx.x;
+  if (i < 3) {
+    unsigned long long t = 0;
+    for (int c = 0; c < ncls; ++c) t += per_class[3 * c + i];
+    total[i] += t;
+  }
 }
 
 // ============================================================== host side
@@ -1123,9 +1376,15 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * KC_NCLASS, st));
   KC_HIP(hipEventRecord(ev_list.a, st));
   int launches = 0;
+  EventPair ev_cls[KC_NCLASS];
+  unsigned long long* cls_ctr;
+  KC_TRY(scr.get(&cls_ctr, 3 * KC_NCLASS));
+  KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * 3 * KC_NCLASS, st));
   for (int cl = KC_NCLASS - 1; cl >= 0; --cl) {
     int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
     if (hi <= lo) continue;
+    KC_TRY(ev_cls[cl].init());
+    KC_HIP(hipEventRecord(ev_cls[cl].a, st));
     ListArgs la;
     la.roots = c.roots;
     la.ri = ri;
@@ -1142,13 +1401,16 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     la.k = c.k;
     la.count = c.count;
     la.pv = c.pv;
-    la.counters = c.counters;
+    la.counters = cls_ctr + 3 * cl;
     la.root_work = c.root_work;
     la.root_isect = c.root_isect;
     la.flags = c.flags;
     KC_TRY(launch_list_class(la, cl, nw, pv, st));
+    KC_HIP(hipEventRecord(ev_cls[cl].b, st));
     launches++;
   }
+  k_add_counters<<<1, 64, 0, st>>>(cls_ctr, KC_NCLASS, c.counters);
+  KC_HIP(hipGetLastError());
   KC_HIP(hipEventRecord(ev_list.b, st));
   if (c.stats) {
     c.stats->stage_ms += ev_stage.ms();
@@ -1156,6 +1418,14 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     c.stats->list_ms += ev_list.ms();
     c.stats->list_launches += launches;
     c.stats->n_tasks += NT;
+    unsigned long long hc[3 * KC_NCLASS];
+    KC_HIP(hipMemcpyAsync(hc, cls_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    for (int cl = 0; cl < KC_NCLASS; ++cl) {
+      if (ev_cls[cl].a) c.stats->class_ms[cl] = ev_cls[cl].ms();
+      c.stats->class_work[cl] = hc[3 * cl + 2];
+      c.stats->class_tasks[cl] = boff[(cl + 1) * 64] - boff[cl * 64];
+    }
   }
   return KC_OK;
 }

@@ -243,6 +243,16 @@ __global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const in
   bin[r] = c * 64 + 63 - kc_key_q(lw);
 }
 
+__global__ void k_sd_add_counters(const unsigned long long* __restrict__ per_class, int ncls,
+                                  unsigned long long* total) {
+  int i = threadIdx.x;
+  if (i < 3) {
+    unsigned long long t = 0;
+    for (int c = 0; c < ncls; ++c) t += per_class[3 * c + i];
+    total[i] += t;
+  }
+}
+
 int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   const int32_t R = c.nroots;
   if (R == 0) return KC_OK;
@@ -263,6 +273,10 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   KC_TRY(scr.get(&heads, SD_NCLASS));
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * SD_NCLASS, st));
   hipEvent_t e0, e1;
+  hipEvent_t ce[SD_NCLASS][2] = {};
+  unsigned long long* cls_ctr;
+  KC_TRY(scr.get(&cls_ctr, 3 * SD_NCLASS));
+  KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * 3 * SD_NCLASS, st));
   KC_HIP(hipEventCreate(&e0));
   KC_HIP(hipEventCreate(&e1));
   KC_HIP(hipEventRecord(e0, st));
@@ -270,6 +284,9 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   for (int cl = SD_NCLASS - 1; cl >= 0; --cl) {
     int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
     if (hi <= lo) continue;
+    KC_HIP(hipEventCreate(&ce[cl][0]));
+    KC_HIP(hipEventCreate(&ce[cl][1]));
+    KC_HIP(hipEventRecord(ce[cl][0], st));
     SdArgs a;
     a.drp = c.drp;
     a.dcol = c.dcol;
@@ -282,7 +299,7 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     a.SMAX = kSClass[cl];
     a.count = c.count;
     a.pv = c.pv;
-    a.counters = c.counters;
+    a.counters = cls_ctr + 3 * cl;
     a.root_work = c.root_work;
     a.root_isect = c.root_isect;
     a.flags = c.flags;
@@ -310,9 +327,12 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds_bytes, st, a);
     KC_HIP(hipGetLastError());
+    KC_HIP(hipEventRecord(ce[cl][1], st));
     launches++;
   }
   KC_HIP(hipEventRecord(e1, st));
+  k_sd_add_counters<<<1, 64, 0, st>>>(cls_ctr, SD_NCLASS, c.counters);
+  KC_HIP(hipGetLastError());
   if (c.stats) {
     float ms = 0.f;
     KC_HIP(hipEventSynchronize(e1));
@@ -320,7 +340,21 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     c.stats->list_ms += ms;
     c.stats->list_launches += launches;
     c.stats->n_tasks += R;
+    unsigned long long hc[3 * SD_NCLASS];
+    KC_HIP(hipMemcpyAsync(hc, cls_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
+    KC_HIP(hipStreamSynchronize(st));
+    for (int cl = 0; cl < SD_NCLASS; ++cl) {
+      if (ce[cl][0]) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ce[cl][0], ce[cl][1]) == hipSuccess) c.stats->class_ms[cl] = t;
+      }
+      c.stats->class_work[cl] = hc[3 * cl + 2];
+      c.stats->class_tasks[cl] = boff[(cl + 1) * 64] - boff[cl * 64];
+    }
   }
+  for (int cl = 0; cl < SD_NCLASS; ++cl)
+    for (int j = 0; j < 2; ++j)
+      if (ce[cl][j]) (void)hipEventDestroy(ce[cl][j]);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return KC_OK;
