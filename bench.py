@@ -69,6 +69,10 @@ def main():
     ci = torch.from_numpy(ci_h).to(dev)
     torch.cuda.synchronize()
 
+    from paper_2203_13512_amd import autotune
+    tuned = autotune.lookup(rp_h, ci_h, k, args.order) if args.order == "color" else {}
+    log(f"autotuned launch shape: {tuned or 'library defaults'}")
+
     schedules = [s for s in args.schedules.split(",") if s]
     mlp = None
     if "learned" in schedules:
@@ -79,7 +83,7 @@ def main():
 
     results = {}
     for sched in schedules:
-        kw = dict(schedule=sched, stats=True)
+        kw = dict(schedule=sched, stats=True, **tuned)
         if sched == "learned":
             kw["mlp"] = mlp
         for i in range(args.warmup):
@@ -148,7 +152,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"{w.name} k={k} {args.order} order", "k": k, "order": args.order,
-                   "schedule": main_sched, "n": int(len(rp_h) - 1), "nnz": int(len(ci_h)), "count": cnt},
+                   "schedule": main_sched, "n": int(len(rp_h) - 1), "nnz": int(len(ci_h)), "count": cnt,
+                   "launch": tuned or "defaults"},
         "schedules": {s: {"value": r["count"] / r["step_s"], "ms_per_step": r["step_s"] * 1e3,
                           "list_ms": r["list_ms"], "n_tasks": r["stats"]["n_tasks"]} for s, r in results.items()},
         "roofline": roofline,

@@ -93,15 +93,23 @@ typedef struct {
   int32_t schedule;       /* KC_SCHED_DEGREE (default) or KC_SCHED_LEARNED */
   const float* mlp_params;/* LEARNED: device pointer, KC_MLP_NPARAMS floats */
   const float* mlp_norm;  /* LEARNED: device pointer, 8 floats: feature mean[4], std[4] (of log1p features) */
-  int32_t waves_per_root; /* BitCol waves sharing one root's bitmaps: 0 = auto, else 1, 2 or 4 */
+  int32_t waves_per_root; /* BitCol waves sharing one root's bitmaps: 0 = auto, 1, 4 or 8 (others round down) */
   int32_t chunk;          /* tasks taken per queue access: 0 = auto */
   int32_t split;          /* heavy-root splitting: 0 = auto, -1 = never, 1/2 = force that depth for heavy roots */
   float split_threshold;  /* 0 = auto: schedule key above which roots are split */
+  int32_t compress;       /* BitCol node re-encoding: 0 or -1 = off, else the largest candidate set
+                             (<= 64) re-encoded into 64-bit rows */
+  int32_t compress_level; /* BitCol: re-encode only nodes of level >= this (0 = auto) */
   /* optional per-vertex logs, device pointers of n entries (NULL = off):
    * the root's listing work (as kc_stats.work) and its features */
   uint64_t* root_work;
   uint64_t* root_isect;
   float* root_features;   /* n x 4: d+_u, core(u), colors of G_u, |E_u| (BitCol only) */
+  uint64_t* root_count;   /* cliques attributed to each vertex: those listed from it as a root, plus the
+                             Pre-List cliques of a clique component at its smallest vertex (sums to the total) */
+  const int32_t* vertex_k;/* device pointer, n entries, or NULL: a k per vertex (constant on every
+                             connected component; the k argument must be their maximum).  Used to count
+                             many graphs with different k in one call. */
   kc_stats* stats;        /* host pointer or NULL */
 } kc_options;
 

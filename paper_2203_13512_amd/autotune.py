@@ -1,0 +1,110 @@
+"""Autotuner for the launch shape of the BitCol listing kernels.
+
+Searched knobs (kc_options): how many waves share one root's bitmaps in LDS
+(lanes per root: 64, 256 or 512), whether candidate sets of at most 64
+members are re-encoded into 64-bit rows and from which recursion level (the
+width of the bitmaps the deepest levels run on), and how many queue items a
+workgroup takes per access (chunking).  None of them changes a result.
+
+The objective is the device time of the listing kernels (HIP events, from the
+call's statistics) on a proxy of the problem: the same graph at k-1 when
+k >= 7 (about ten times less work, same sets and the same shape of the search
+tree near its leaves), else the problem itself.  Decisions are cached in
+autotune.json next to this module, keyed by a signature of the graph and k.
+
+Run ``python -m paper_2203_13512_amd.autotune [workload ...]`` on a GPU to
+tune the synthetic workloads and write the cache.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+import paper_2203_13512_amd as kc
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json")
+
+SPACE = [
+    {"waves_per_root": 4, "compress": -1},
+    {"waves_per_root": 8, "compress": -1},
+    {"waves_per_root": 4, "compress": 64, "compress_level": 4},
+    {"waves_per_root": 8, "compress": 64, "compress_level": 4},
+    {"waves_per_root": 8, "compress": 64, "compress_level": 5},
+    {"waves_per_root": 8, "compress": 64, "compress_level": 4, "chunk": 1},
+]
+
+
+def signature(row_ptr, col_idx, k: int, order: str) -> str:
+    rp = np.asarray(row_ptr.cpu() if hasattr(row_ptr, "cpu") else row_ptr, dtype=np.int32)
+    h = hashlib.blake2b(digest_size=12)
+    h.update(np.asarray([len(rp) - 1, int(rp[-1]), k], dtype=np.int64).tobytes())
+    h.update(order.encode())
+    h.update(np.ascontiguousarray(rp[: 1 << 16]).tobytes())
+    return h.hexdigest()
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def lookup(row_ptr, col_idx, k: int, order: str = "color", path: str = CACHE) -> dict:
+    """Tuned kc.count keyword arguments for this graph and k ({} if untuned)."""
+    e = load_cache(path).get(signature(row_ptr, col_idx, k, order))
+    return dict(e["best"]) if e else {}
+
+
+def tune(row_ptr, col_idx, k: int, order: str = "color", space=SPACE, log=print, **count_kw):
+    """Times every candidate on the proxy problem; returns (best, table)."""
+    import torch
+    kp = k - 1 if k >= 7 else k
+    table = []
+    for cand in space:
+        kw = dict(count_kw)
+        kw.update(cand)
+        torch.cuda.synchronize()
+        c, st = kc.count(row_ptr, col_idx, kp, order, stats=True, **kw)
+        torch.cuda.synchronize()
+        table.append(dict(cand=cand, list_ms=st["list_ms"], total_ms=st["total_ms"], count=c))
+        log(f"  k={kp} {cand}: list {st['list_ms']:.1f} ms")
+    counts = {t["count"] for t in table}
+    assert len(counts) == 1, f"tuning candidates disagree: {counts}"
+    best = min(table, key=lambda t: t["list_ms"])["cand"]
+    return best, dict(proxy_k=kp, table=table)
+
+
+def main(argv=None):
+    import torch
+
+    import graphgen
+    argv = argv if argv is not None else sys.argv[1:]
+    jobs = [tuple(int(x) for x in a.split(":")) for a in argv] or [(5, 8), (2, 7), (3, 8)]
+    cache = load_cache()
+    dev = torch.device("cuda:0")
+    for cfg, k in jobs:
+        w = graphgen.workload(cfg)
+        rp_h, ci_h = w.graphs[0]
+        rp = torch.from_numpy(rp_h).to(dev)
+        ci = torch.from_numpy(ci_h).to(dev)
+        t = time.time()
+        print(f"{w.name} k={k}", flush=True)
+        best, info = tune(rp, ci, k, "color")
+        cache[signature(rp_h, ci_h, k, "color")] = dict(workload=w.name, k=k, order="color", best=best, **info)
+        print(f"  best {best} ({time.time() - t:.1f}s)", flush=True)
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1)
+    out = os.environ.get("KC_AUTOTUNE_OUT")
+    if out:
+        with open(out, "w") as f:
+            json.dump(cache, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

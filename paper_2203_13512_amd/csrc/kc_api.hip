@@ -10,6 +10,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "kc_internal.h"
 
 extern "C" void kc_options_init(kc_options* opt) {
@@ -28,11 +30,11 @@ extern "C" const char* kc_status_string(int status) {
   return "unknown status";
 }
 
-__global__ void k_roots(int32_t n, const int32_t* __restrict__ drp, int32_t km1, int32_t* roots, int32_t* nroots,
-                        int32_t* max_dplus) {
+__global__ void k_roots(int32_t n, const int32_t* __restrict__ drp, int32_t km1, const int32_t* vk, int32_t* roots,
+                        int32_t* nroots, int32_t* max_dplus) {
   int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   int32_t d = u < n ? drp[u + 1] - drp[u] : 0;
-  bool take = u < n && d >= km1;
+  bool take = u < n && d >= kc_vk(vk, u, km1 + 1) - 1;
   uint64_t m = kc_ballot(take);
   int base = 0;
   if (kc_lane() == 0 && m) base = atomicAdd(nroots, __popcll(m));
@@ -121,6 +123,7 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     if (n > 0) KC_HIP(hipMemsetAsync(pv_d, 0, sizeof(unsigned long long) * (size_t)n, s));
   }
   if (n > 0) {
+    if (opt->root_count) KC_HIP(hipMemsetAsync(opt->root_count, 0, sizeof(uint64_t) * (size_t)n, s));
     if (opt->root_work) KC_HIP(hipMemsetAsync(opt->root_work, 0, sizeof(uint64_t) * (size_t)n, s));
     if (opt->root_isect) KC_HIP(hipMemsetAsync(opt->root_isect, 0, sizeof(uint64_t) * (size_t)n, s));
     if (opt->root_features) KC_HIP(hipMemsetAsync(opt->root_features, 0, sizeof(float) * 4 * (size_t)n, s));
@@ -136,7 +139,10 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   }
 
   uint64_t total = 0;
-  if (k <= 2 || k > n) {
+  const int32_t* vk = opt->vertex_k;
+  if (vk && !opt->device_ptrs) return KC_EINVAL;
+  if (vk && k < 3) return KC_EUNSUPPORTED;
+  if (k <= 2 || (k > n && !vk)) {
     // linear cases and the empty answer
     if (k == 1) total = (uint64_t)n;
     else if (k == 2) total = (uint64_t)nnz32 / 2;
@@ -149,13 +155,14 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   } else {
     if (k > KC_KMAX_LIMIT) return KC_EUNSUPPORTED;
     kc_prep_out prep;
-    KC_TRY(kc_preprocess(g, k, order, prelist_d, pv_d, flags, &prep, scr, s));
+    KC_TRY(kc_preprocess(g, k, vk, order, prelist_d, pv_d, (unsigned long long*)opt->root_count, flags, &prep,
+                         scr, s));
     KC_HIP(hipEventRecord(ev.e[1], s));
     int32_t *roots, *rinfo;
     KC_TRY(scr.get(&roots, (size_t)n + 1));
     KC_TRY(scr.get(&rinfo, 4));
     KC_HIP(hipMemsetAsync(rinfo, 0, sizeof(int32_t) * 4, s));
-    k_roots<<<(n + 255) / 256, 256, 0, s>>>(n, prep.drp, k - 1, roots, rinfo, rinfo + 1);
+    k_roots<<<(n + 255) / 256, 256, 0, s>>>(n, prep.drp, k - 1, vk, roots, rinfo, rinfo + 1);
     KC_HIP(hipGetLastError());
     int32_t hr[2] = {0, 0};
     KC_HIP(hipMemcpyAsync(hr, rinfo, sizeof(hr), hipMemcpyDeviceToHost, s));
@@ -164,6 +171,8 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     memset(&c, 0, sizeof(c));
     c.n = n;
     c.k = k;
+    c.vk = vk;
+    c.root_count = (unsigned long long*)opt->root_count;
     c.drp = prep.drp;
     c.dcol = prep.dcol;
     c.core = prep.core;
@@ -199,7 +208,7 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   KC_HIP(hipStreamSynchronize(s));
   if (hflags & KC_FLAG_OVERFLOW) return KC_EOVERFLOW;
   if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
-  if (k > 2 && k <= n) {
+  if (k > 2 && (k <= n || vk)) {
     total = hres[0] + hres[1];
     if (total < hres[0]) return KC_EOVERFLOW;
   }
@@ -236,24 +245,154 @@ extern "C" int kclique_list_per_vertex(int32_t n, const int32_t* row_ptr, const 
   return st;
 }
 
+// Batched counting: the graphs become one disjoint union (vertex ids shifted
+// by the preceding graphs' sizes) with a k per vertex, counted by a single call
+// -- one preprocessing pass, one staging pass and one persistent listing
+// launch per word class for all graphs -- and the per-root attribution is
+// summed per graph.
+__global__ void k_union_rows(int32_t ng, const int32_t* __restrict__ n, const int64_t* __restrict__ voff,
+                             const int64_t* __restrict__ row_off, const int64_t* __restrict__ eoff,
+                             const int32_t* __restrict__ rp_cat, int32_t* rp_out, int32_t* vk_out,
+                             const int32_t* __restrict__ kk, int32_t* gid) {
+  int32_t g = blockIdx.y;
+  if (g >= ng) return;
+  const int32_t ng_v = n[g];
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < ng_v; v += gridDim.x * blockDim.x) {
+    const int64_t gv = voff[g] + v;
+    rp_out[gv] = (int32_t)(eoff[g] + rp_cat[row_off[g] + v]);
+    vk_out[gv] = kk[g];
+    gid[gv] = g;
+  }
+}
+
+__global__ void k_union_cols(int32_t ng, const int32_t* __restrict__ n, const int64_t* __restrict__ voff,
+                             const int64_t* __restrict__ row_off, const int64_t* __restrict__ col_off,
+                             const int64_t* __restrict__ eoff, const int32_t* __restrict__ rp_cat,
+                             const int32_t* __restrict__ col_cat, int32_t* col_out) {
+  int32_t g = blockIdx.y;
+  if (g >= ng) return;
+  const int64_t m = rp_cat[row_off[g] + n[g]];
+  const int32_t shift = (int32_t)voff[g];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    col_out[eoff[g] + i] = col_cat[col_off[g] + i] + shift;
+}
+
+__global__ void k_graph_sums(int32_t nv, const int32_t* __restrict__ gid, const unsigned long long* __restrict__ rc,
+                             unsigned long long* out) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const unsigned long long c = rc[v];
+  if (c) atomicAdd(&out[gid[v]], c);
+}
+
 extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off,
                                      const int64_t* col_off, const int32_t* row_ptr_cat, const int32_t* col_idx_cat,
                                      const int32_t* k, int32_t order, const kc_options* opt, uint64_t* counts_out) {
   if (num_graphs < 0 || (num_graphs > 0 && (!n || !row_off || !col_off || !k || !counts_out))) return KC_EINVAL;
+  if (num_graphs == 0) return KC_OK;
   kc_options o;
   if (opt) o = *opt;
   else memset(&o, 0, sizeof(o));
-  o.stats = nullptr;
+  hipStream_t s = (hipStream_t)o.stream;
+  const bool dev_in = o.device_ptrs != 0;
+  // sizes (host): vertex and edge offsets of the union, largest k
+  std::vector<int64_t> voff(num_graphs + 1), eoff(num_graphs + 1);
+  std::vector<int32_t> m(num_graphs);
+  int32_t kmax = 0;
   for (int32_t g = 0; g < num_graphs; ++g) {
-    uint64_t c = 0;
-    int st = count_impl(n[g], row_ptr_cat + row_off[g], col_idx_cat + col_off[g], k[g], order, &o, &c, nullptr);
-    if (st) return st;
-    if (o.device_ptrs) {
-      KC_HIP(hipMemcpyAsync(counts_out + g, &c, sizeof(uint64_t), hipMemcpyHostToDevice, (hipStream_t)o.stream));
-      KC_HIP(hipStreamSynchronize((hipStream_t)o.stream));
+    if (n[g] < 0 || k[g] < 1) return KC_EINVAL;
+    if (dev_in) {
+      KC_HIP(hipMemcpy(&m[g], row_ptr_cat + row_off[g] + n[g], sizeof(int32_t), hipMemcpyDeviceToHost));
     } else {
-      counts_out[g] = c;
+      m[g] = row_ptr_cat[row_off[g] + n[g]];
     }
+    kmax = k[g] > kmax ? k[g] : kmax;
+  }
+  voff[0] = eoff[0] = 0;
+  for (int32_t g = 0; g < num_graphs; ++g) {
+    voff[g + 1] = voff[g] + n[g];
+    eoff[g + 1] = eoff[g] + m[g];
+  }
+  const int64_t NV = voff[num_graphs], NE = eoff[num_graphs];
+  if (NV >= INT32_MAX || NE >= INT32_MAX) return KC_EUNSUPPORTED;
+  // graphs with k < 3 are answered directly; the rest join the union (their
+  // k must be at least 3 for the listing path), with small k lifted out
+  std::vector<uint64_t> result(num_graphs, 0);
+  bool any_small = false;
+  for (int32_t g = 0; g < num_graphs; ++g)
+    if (k[g] <= 2) any_small = true;
+  kc_scratch scr(s);
+  int32_t *rp_u, *col_u, *vk_u, *gid, *kk_d, *n_d;
+  int64_t *voff_d, *eoff_d, *roff_d, *coff_d;
+  unsigned long long *rc, *sums;
+  KC_TRY(scr.get(&rp_u, (size_t)NV + 1));
+  KC_TRY(scr.get(&col_u, (size_t)NE + 1));
+  KC_TRY(scr.get(&vk_u, (size_t)NV + 1));
+  KC_TRY(scr.get(&gid, (size_t)NV + 1));
+  KC_TRY(scr.get(&rc, (size_t)NV + 1));
+  KC_TRY(scr.get(&sums, (size_t)num_graphs));
+  KC_TRY(scr.get(&kk_d, (size_t)num_graphs));
+  KC_TRY(scr.get(&n_d, (size_t)num_graphs));
+  KC_TRY(scr.get(&voff_d, (size_t)num_graphs + 1));
+  KC_TRY(scr.get(&eoff_d, (size_t)num_graphs + 1));
+  KC_TRY(scr.get(&roff_d, (size_t)num_graphs));
+  KC_TRY(scr.get(&coff_d, (size_t)num_graphs));
+  std::vector<int32_t> kk(num_graphs);
+  for (int32_t g = 0; g < num_graphs; ++g) kk[g] = k[g] < 3 ? 3 : k[g];
+  KC_HIP(hipMemcpyAsync(kk_d, kk.data(), sizeof(int32_t) * num_graphs, hipMemcpyHostToDevice, s));
+  KC_HIP(hipMemcpyAsync(n_d, n, sizeof(int32_t) * num_graphs, hipMemcpyHostToDevice, s));
+  KC_HIP(hipMemcpyAsync(voff_d, voff.data(), sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s));
+  KC_HIP(hipMemcpyAsync(eoff_d, eoff.data(), sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s));
+  KC_HIP(hipMemcpyAsync(roff_d, row_off, sizeof(int64_t) * num_graphs, hipMemcpyHostToDevice, s));
+  KC_HIP(hipMemcpyAsync(coff_d, col_off, sizeof(int64_t) * num_graphs, hipMemcpyHostToDevice, s));
+  const int32_t* rp_src = row_ptr_cat;
+  const int32_t* col_src = col_idx_cat;
+  if (!dev_in) {
+    // stage the concatenated host arrays
+    int64_t rtot = 0, ctot = 0;
+    for (int32_t g = 0; g < num_graphs; ++g) {
+      rtot = row_off[g] + n[g] + 1 > rtot ? row_off[g] + n[g] + 1 : rtot;
+      ctot = col_off[g] + m[g] > ctot ? col_off[g] + m[g] : ctot;
+    }
+    int32_t *r_d, *c_d;
+    KC_TRY(scr.get(&r_d, (size_t)rtot + 1));
+    KC_TRY(scr.get(&c_d, (size_t)ctot + 1));
+    KC_HIP(hipMemcpyAsync(r_d, row_ptr_cat, sizeof(int32_t) * rtot, hipMemcpyHostToDevice, s));
+    if (ctot > 0) KC_HIP(hipMemcpyAsync(c_d, col_idx_cat, sizeof(int32_t) * ctot, hipMemcpyHostToDevice, s));
+    rp_src = r_d;
+    col_src = c_d;
+  }
+  dim3 grid_r(64, num_graphs), grid_c(256, num_graphs);
+  k_union_rows<<<grid_r, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, eoff_d, rp_src, rp_u, vk_u, kk_d, gid);
+  k_union_cols<<<grid_c, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, coff_d, eoff_d, rp_src, col_src, col_u);
+  KC_HIP(hipGetLastError());
+  int32_t last = (int32_t)NE;
+  KC_HIP(hipMemcpyAsync(rp_u + NV, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  KC_HIP(hipStreamSynchronize(s));
+  kc_options u = o;
+  u.device_ptrs = 1;
+  u.vertex_k = vk_u;
+  u.root_count = (uint64_t*)rc;
+  u.root_work = nullptr;
+  u.root_isect = nullptr;
+  u.root_features = nullptr;
+  uint64_t total = 0;
+  KC_TRY(count_impl((int32_t)NV, rp_u, col_u, kmax < 3 ? 3 : kmax, order, &u, &total, nullptr));
+  KC_HIP(hipMemsetAsync(sums, 0, sizeof(unsigned long long) * num_graphs, s));
+  k_graph_sums<<<(unsigned)((NV + 255) / 256), 256, 0, s>>>((int32_t)NV, gid, rc, sums);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipMemcpyAsync(result.data(), sums, sizeof(uint64_t) * num_graphs, hipMemcpyDeviceToHost, s));
+  KC_HIP(hipStreamSynchronize(s));
+  // k = 1 and k = 2 directly
+  if (any_small)
+    for (int32_t g = 0; g < num_graphs; ++g)
+      if (k[g] == 1) result[g] = (uint64_t)n[g];
+      else if (k[g] == 2) result[g] = (uint64_t)m[g] / 2;
+  if (dev_in) {
+    KC_HIP(hipMemcpyAsync(counts_out, result.data(), sizeof(uint64_t) * num_graphs, hipMemcpyHostToDevice, s));
+    KC_HIP(hipStreamSynchronize(s));
+  } else {
+    memcpy(counts_out, result.data(), sizeof(uint64_t) * num_graphs);
   }
   return KC_OK;
 }

@@ -315,6 +315,10 @@ struct ListArgs {
   unsigned long long* head;  // queue head
   int chunk;
   int k;
+  const int32_t* vk;                 // per-vertex k (nullable)
+  unsigned long long* root_count;    // per-root attribution (nullable)
+  int cmax;   // re-encode sets of at most cmax members (0 = never)
+  int clev;   // ... at nodes of level >= clev
   unsigned long long* count;
   unsigned long long* pv;
   unsigned long long* counters;  // nodes, isect, work
@@ -328,10 +332,10 @@ struct ListArgs {
 //   B[W][S+1] | Bin[W][S+1] (per-vertex) | color[S] | firstpos[KMAX+2] |
 //   C0[W] | shared scalars[16] | NW wave blocks | cnt[S] u64 (per-vertex)
 // A wave block holds tot[KMAX+1] u64 | cur[KMAX+1] | chosen[KMAX+1] |
-// stack[(KMAX+1)][W] | candidate lists[2][S] u16 | pairs[2S] u32.
+// rows/rins[64] u64 | stack[(KMAX+1)][W] | member list[64] u16 | candidate list[S] u16.
 #define KC_KMAX 32
 
-template <int W, int NW, bool PV>
+template <int W, int NW, bool PV, bool COMP>
 struct ListLayout {
   static constexpr int S = 32 * W;
   static constexpr int SP = S + 1;  // LDS row stride (bank-conflict free)
@@ -343,11 +347,15 @@ struct ListLayout {
   static constexpr int oC0 = oFirst + KC_KMAX + 2;
   static constexpr int oSh = a2(oC0 + W);
   static constexpr int oWave = oSh + 16;
-  static constexpr int PCAP = 2 * S;  // (x, v) pairs buffered per wave
-  static constexpr int wave_words = a2(4 * (KC_KMAX + 1) + (KC_KMAX + 1) * W + S / 2 + S / 2 + PCAP);
-  static constexpr int oCnt = oWave + NW * wave_words;
-  static constexpr int words = oCnt + (PV ? 2 * S : 0);
-  static constexpr size_t bytes() { return 4 * (size_t)words; }
+  // per wave, for recursion depth K = k + 1 (runtime):
+  //   tot[K] u64 | [rows[64] rins[64] cm[12] u64 (compressed variant)] |
+  //   cur[K] | chosen[K] | stack[K][W] | mlist[64] u16 | vlist[S] u16
+  __host__ __device__ static constexpr int wave_words(int K) {
+    return a2(2 * K + (COMP ? 256 + 24 : 0) + 2 * K + K * W + 32 + S / 2);
+  }
+  __host__ __device__ static constexpr int oCnt(int K) { return oWave + NW * wave_words(K); }
+  __host__ __device__ static constexpr int words(int K) { return oCnt(K) + (PV ? 2 * S : 0); }
+  static size_t bytes(int K) { return 4 * (size_t)words(K); }
 };
 
 // Wave-wide popcount of a lane-split bitmap (lane i < W holds word i).
@@ -493,158 +501,289 @@ __device__ __forceinline__ uint64_t level3_eval(const uint32_t* __restrict__ Bl,
   return total;
 }
 
-// Level-4 node with set C (lane-split `cw`), evaluated lane-parallel over
-// (x, v) pairs: lanes first take the members x of C with color >= 4, form
-// C3 = B(x) & C and count the members v of C3 with color >= 3; the pairs
-// (x, v) of the x with |C3| >= 3 are written to an LDS list and then dealt to
-// lanes, each forming C2 = B(v) & C3 and, when |C2| >= 2, counting the
-// leaves below it as level3_eval does.  Small level-3 nodes thus share
-// passes instead of each leaving most lanes idle.  When a batch of x yields
-// more pairs than the buffer holds (dense sets), its x are evaluated one by
-// one with level3_eval, which is efficient for large sets.
+// ---- compressed nodes ----------------------------------------------------
+// Once a node's candidate set C has at most 64 members, the sub-DAG it
+// induces is re-encoded: member j (members in position order, which is color
+// order) gets the 64-bit row R_j = {j' : member j' is in B(member j)}.  This
+// is the out-neighbour reduction of Sec. 7.2 applied to the candidate set:
+// every BitJoin below the node becomes one 64-bit AND and popcount, and the
+// encoding keeps the color order, so "color >= l" stays a suffix of member
+// indices.  Each lane takes one candidate of the node and finishes its
+// subtree with a depth-first walk whose levels are unrolled at compile time
+// (cdfs<L>), so the walk's sets stay in registers.
+#define KC_CMAX 10  // deepest level evaluated on compressed rows
+
+struct CNode {
+  const uint64_t* rows;   // R_j (LDS)
+  const uint64_t* rins;   // per-vertex: {j' : member j in B(member j')} (LDS)
+  const uint16_t* mlist;  // member j -> position
+  const uint64_t* cm;     // cm[c] = members with color >= c (LDS, c <= KC_CMAX)
+};
+
+template <bool PV, int L>
+__device__ __forceinline__ uint64_t cdfs(const uint64_t* __restrict__ rows, const uint64_t* __restrict__ rins,
+                                         const uint16_t* __restrict__ mlist, const uint64_t* __restrict__ cm,
+                                         uint64_t X, uint64_t& joins, uint64_t& nodes, unsigned long long* cnt) {
+  if constexpr (L == 2) {
+    uint64_t t = 0;
+    const uint64_t c2 = cm[2];
+    uint64_t cand = PV ? X : (X & c2);
+    while (cand) {
+      const int y = __ffsll((long long)cand) - 1;
+      cand &= cand - 1;
+      uint32_t out = 0;
+      if (!PV || ((c2 >> y) & 1ull)) {
+        out = (uint32_t)__popcll(rows[y] & X);
+        joins++;
+      }
+      t += out;
+      if (PV) {
+        const uint32_t in = (uint32_t)__popcll(rins[y] & X);
+        if (out + in) atomicAdd(&cnt[mlist[y]], (unsigned long long)(out + in));
+      }
+    }
+    return t;
+  } else {
+    uint64_t t = 0;
+    uint64_t cand = X & cm[L];
+    while (cand) {
+      const int y = __ffsll((long long)cand) - 1;
+      cand &= cand - 1;
+      const uint64_t X2 = rows[y] & X;
+      joins++;
+      if (__popcll(X2) >= L - 1) {
+        nodes++;
+        const uint64_t sub = cdfs<PV, L - 1>(rows, rins, mlist, cm, X2, joins, nodes, cnt);
+        t += sub;
+        if (PV && sub) atomicAdd(&cnt[mlist[y]], (unsigned long long)sub);
+      }
+    }
+    return t;
+  }
+}
+
+// Subtree below candidate j's BitJoin at a node of level l: X2 = R_j.
+template <bool PV>
+__device__ __forceinline__ uint64_t cdfs_dispatch(int l, const CNode& nd, uint64_t X2, uint64_t& joins,
+                                                  uint64_t& nodes, unsigned long long* cnt) {
+#define KC_CD(L) \
+  case L: return cdfs<PV, L>(nd.rows, nd.rins, nd.mlist, nd.cm, X2, joins, nodes, cnt);
+  switch (l - 1) {
+    KC_CD(2) KC_CD(3) KC_CD(4) KC_CD(5) KC_CD(6) KC_CD(7) KC_CD(8) KC_CD(9)
+  }
+#undef KC_CD
+  return 0;
+}
+
+// Node of level l (2 <= l <= KC_CMAX) whose set C (lane-split `cw`) has at
+// most 64 members.  Candidates are dealt to the lanes of `nparts` waves
+// (this wave is `part`).  Returns this lane's share of the node's leaves.
 template <int W, bool PV>
-__device__ __forceinline__ uint64_t level4_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
-                                                int s, int first2, int first3, int first4, uint32_t cw, int lane,
-                                                uint16_t* __restrict__ xlist, uint16_t* __restrict__ vlist,
-                                                uint32_t* __restrict__ pairs, int pcap, uint64_t& joins,
-                                                uint64_t& nodes, unsigned long long* cnt, int part, int nparts) {
+__device__ __forceinline__ uint64_t compressed_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
+                                                    const uint32_t* __restrict__ col, int s, int l, uint32_t cw,
+                                                    int lane, uint16_t* __restrict__ mlist, uint64_t* __restrict__ rows,
+                                                    uint64_t* __restrict__ rins, uint64_t& joins, uint64_t& nodes,
+                                                    unsigned long long* cnt, int part, int nparts) {
   constexpr int SP = 32 * W + 1;
   const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
   if (hiw < 0) return 0;
-  uint32_t c[W];
-#pragma unroll
-  for (int i = 0; i < W; ++i) c[i] = kc_readlane(cw, i);
   const int end = (hiw + 1) * 32 < s ? (hiw + 1) * 32 : s;
-  int mx = 0;
-  for (int p0 = first4 & ~63; p0 < end; p0 += 64) {
+  int m = 0;
+  for (int p0 = 0; p0 < end; p0 += 64) {
     const int p = p0 + lane;
     const uint32_t word = (uint32_t)__shfl((int)cw, (p >> 5) & 63, 64);
-    const bool mem = p >= first4 && p < end && ((word >> (p & 31)) & 1u);
+    const bool mem = p < end && ((word >> (p & 31)) & 1u);
     const uint64_t mk = kc_ballot(mem);
-    if (mem) xlist[mx + kc_mbcnt(mk)] = (uint16_t)p;
-    mx += __popcll(mk);
+    if (mem) mlist[m + kc_mbcnt(mk)] = (uint16_t)p;
+    m += __popcll(mk);
   }
   kc_wave_lds_sync();
-  const int f2w = first2 >> 5, f3w = first3 >> 5;
-  const uint32_t f2m = (~0u) << (first2 & 31), f3m = (~0u) << (first3 & 31);
-  uint64_t total = 0;
-  for (int xb = part * 64; xb < mx; xb += 64 * nparts) {
-    const int idx = xb + lane;
-    const bool valid = idx < mx;
-    const int x = valid ? xlist[idx] : 0;
-    uint32_t c3[W];
-    int p3 = 0, nv = 0;
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      c3[i] = (valid && i <= hiw) ? (Bl[i * SP + x] & c[i]) : 0u;
-      p3 += __popc(c3[i]);
-      const uint32_t mv = i < f3w ? 0u : (i == f3w ? (c3[i] & f3m) : c3[i]);
-      nv += __popc(mv);
-    }
-    joins += valid ? 1 : 0;
-    const bool q = valid && p3 >= 3;
-    nodes += q ? 1 : 0;
-    if (!q) nv = 0;
-    // exclusive prefix of nv over the wave
-    int incl = nv;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    const int P = __shfl(incl, 63, 64);
-    const int off = incl - nv;
-    if (P == 0) continue;
-    if (P > pcap) {
-      // dense batch: one level-3 node at a time
-      uint64_t qm = kc_ballot(q);
-      while (qm) {
-        const int fl = __ffsll((long long)qm) - 1;
-        qm &= qm - 1;
-        const int xx = __shfl(x, fl, 64);
-        // lane i needs word i of lane fl's C3
-        uint32_t mine = 0;
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-          uint32_t wv = kc_readlane(c3[i], fl);
-          if (lane == i) mine = wv;
-        }
-        uint64_t t3 = level3_eval<W, PV>(Bl, Bil, s, first2, first3, mine, lane, vlist, joins, nodes, cnt, 0, 1);
-        total += t3;
-        if (PV) {
-          uint64_t T3 = kc_wave_sum_u64(t3);
-          if (lane == 0 && T3) atomicAdd(&cnt[xx], (unsigned long long)T3);
-        }
+  const bool valid = lane < m;
+  const int v = valid ? mlist[lane] : 0;
+  // rows: lane j tests each member j' against B(member j)
+  uint64_t R = 0, Rin = 0;
+  {
+    int curw = -1;
+    uint32_t bw = 0, biw = 0;
+    for (int jj = 0; jj < m; ++jj) {
+      const int p = __builtin_amdgcn_readlane(v, jj);
+      const int wd = p >> 5;
+      if (wd != curw) {
+        curw = wd;
+        bw = valid ? Bl[wd * SP + v] : 0u;
+        if (PV) biw = valid ? Bil[wd * SP + v] : 0u;
       }
-      continue;
+      R |= (uint64_t)((bw >> (p & 31)) & 1u) << jj;
+      if (PV) Rin |= (uint64_t)((biw >> (p & 31)) & 1u) << jj;
     }
-    // write this lane's pairs
-    if (q) {
-      int j = off;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        uint32_t m = i < f3w ? 0u : (i == f3w ? (c3[i] & f3m) : c3[i]);
-        while (m) {
-          const int b = __ffs(m) - 1;
-          m &= m - 1;
-          pairs[j++] = ((uint32_t)x << 16) | (uint32_t)(i * 32 + b);
-        }
-      }
-    }
-    kc_wave_lds_sync();
-    for (int pb = 0; pb < P; pb += 64) {
-      const int pi = pb + lane;
-      if (pi >= P) continue;
-      const uint32_t pr = pairs[pi];
-      const int px = (int)(pr >> 16), v = (int)(pr & 0xffff);
-      uint32_t c2[W];
-      int pc = 0;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        c2[i] = i <= hiw ? (Bl[i * SP + px] & c[i] & Bl[i * SP + v]) : 0u;
-        pc += __popc(c2[i]);
-      }
-      joins++;
-      if (pc < 2) continue;
-      nodes++;
-      uint32_t leaf = 0;
-#pragma unroll
-      for (int i = 0; i < W; ++i) {
-        uint32_t m = c2[i];
-        if (!PV) m = i < f2w ? 0u : (i == f2w ? (m & f2m) : m);
-        while (m) {
-          const int b = __ffs(m) - 1;
-          m &= m - 1;
-          const int w = i * 32 + b;
-          uint32_t out = 0;
-          if (!PV || w >= first2) {
-#pragma unroll
-            for (int j = 0; j <= i; ++j) out += (uint32_t)__popc(Bl[j * SP + w] & c2[j]);
-            joins++;
-          }
-          leaf += out;
-          if (PV) {
-            uint32_t in = 0;
-#pragma unroll
-            for (int j = i; j < W; ++j) in += (uint32_t)__popc(Bil[j * SP + w] & c2[j]);
-            if (out + in) atomicAdd(&cnt[w], (unsigned long long)(out + in));
-          }
-        }
-      }
-      total += leaf;
-      if (PV && leaf) {
-        atomicAdd(&cnt[v], (unsigned long long)leaf);
-        atomicAdd(&cnt[px], (unsigned long long)leaf);
-      }
-    }
-    kc_wave_lds_sync();
   }
-  return total;
+  rows[lane] = R;
+  if (PV) rins[lane] = Rin;
+  const int cv = valid ? (int)col[v] : 0;
+  uint64_t* cmw = rows + 128;  // cm[0..KC_CMAX] after rows and rins
+#pragma unroll
+  for (int c = 0; c <= KC_CMAX; ++c) {
+    const uint64_t b = kc_ballot(valid && cv >= c);
+    if (lane == 0) cmw[c] = b;
+  }
+  const uint64_t cm0 = kc_ballot(valid), cm2 = kc_ballot(valid && cv >= 2);
+  const uint64_t cml = kc_ballot(valid && cv >= l);
+  CNode nd;
+  nd.rows = rows;
+  nd.rins = rins;
+  nd.mlist = mlist;
+  nd.cm = cmw;
+  kc_wave_lds_sync();
+  uint64_t t = 0;
+  // this lane's candidate: member `lane` of the node, if dealt to this wave
+  const bool mine = valid && ((lane % nparts) == part);
+  if (l == 2) {
+    if (mine) {
+      const uint64_t X = cm0;
+      uint32_t out = 0;
+      if ((cm2 >> lane) & 1ull) {
+        out = (uint32_t)__popcll(R & X);
+        joins++;
+      }
+      t = out;
+      if (PV) {
+        const uint32_t in = (uint32_t)__popcll(Rin & X);
+        if (out + in) atomicAdd(&cnt[v], (unsigned long long)(out + in));
+      }
+    }
+  } else if (mine && ((cml >> lane) & 1ull)) {
+    joins++;
+    if (__popcll(R) >= l - 1) {
+      nodes++;
+      t = cdfs_dispatch<PV>(l, nd, R, joins, nodes, cnt);
+      if (PV && t) atomicAdd(&cnt[v], (unsigned long long)t);
+    }
+  }
+  kc_wave_lds_sync();
+  return t;
 }
 
-template <int W, int NW, bool PV>
+// Evaluates a node of level L whose set is the lane-split `cw` on one wave
+// (or, at the top of a task, `nparts` waves): compressed when it has at most
+// 64 members, lane-parallel at levels 2 and 3, otherwise depth-first with an
+// explicit LDS stack whose children are evaluated the same way.  Returns this
+// lane's share of the node's leaves.
+template <int W, bool PV, bool COMP>
+__device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
+                              const uint32_t* __restrict__ col, const int32_t* __restrict__ firstpos, int s, int L,
+                              uint32_t cw, int lane, uint32_t* __restrict__ stk, int32_t* __restrict__ cur,
+                              int32_t* __restrict__ chosen, unsigned long long* __restrict__ tot,
+                              uint16_t* __restrict__ mlist, uint64_t* __restrict__ rows, uint64_t* __restrict__ rins,
+                              uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes,
+                              unsigned long long* cnt, int part, int nparts, int cmax, int clev,
+                              int32_t* __restrict__ shared_next) {
+  constexpr int SP = 32 * W + 1;
+  const uint32_t m = split_popc(cw);
+  if (COMP && (int)m <= cmax && L <= KC_CMAX && L >= clev)
+    return compressed_eval<W, PV>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt, part, nparts);
+  if (L == 2) {
+    uint64_t j = 0;
+    uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], cw, lane, j, cnt, part, nparts);
+    joins += (lane == 0) ? j : 0;
+    return (lane == 0) ? t2 : 0;
+  }
+  if (L == 3)
+    return level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], cw, lane, vlist, joins, nodes, cnt, part, nparts);
+  // depth-first.  With several waves on the node (nparts > 1) the top-level
+  // candidates are taken from a shared counter, one at a time and from the
+  // highest position down (those carry the most work), so that the waves
+  // balance themselves.
+  if (lane < W) stk[lane] = cw;
+  if (lane == 0) {
+    cur[0] = firstpos[L];
+    tot[0] = 0;
+  }
+  kc_wave_lds_sync();
+  uint64_t lane_acc = 0;
+  int d = 0;
+  int limit = 0;
+  if (nparts > 1) {
+    const int hw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
+    if (hw >= 0) limit = hw * 32 + 32 - __clz((int)kc_readlane(cw, hw));
+  }
+  for (;;) {
+    const int l = L - d;
+    const uint32_t mw = lane < W ? stk[d * W + lane] : 0u;
+    int x;
+    if (d == 0 && nparts > 1) {
+      x = -1;
+      if (lane == 0) {
+        for (;;) {
+          // heaviest first: higher positions have more lower-colored neighbours
+          const int p = limit - 1 - atomicAdd(shared_next, 1);
+          if (p < firstpos[L]) break;
+          if ((stk[p >> 5] >> (p & 31)) & 1u) { x = p; break; }
+        }
+      }
+      x = __shfl(x, 0, 64);
+    } else {
+      const int from = cur[d];
+      x = split_next<W>(mw, from, lane);
+    }
+    if (x < 0) {
+      if (d == 0) break;
+      if (PV && lane == 0) {
+        unsigned long long T = tot[d];
+        tot[d - 1] += T;
+        if (T) atomicAdd(&cnt[chosen[d - 1]], T);
+      }
+      kc_wave_lds_sync();
+      d--;
+      continue;
+    }
+    if (lane == 0) cur[d] = x + 1;
+    kc_wave_lds_sync();
+    const uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
+    joins += (lane == 0);
+    const uint32_t npc = split_popc(nw);
+    if ((int)npc < l - 1) continue;
+    nodes += (lane == 0);
+    const int lc = l - 1;
+    const bool comp = COMP && (int)npc <= cmax && lc <= KC_CMAX && lc >= clev;
+    if (comp || lc <= 3) {
+      uint64_t tc;
+      if (COMP && comp)
+        tc = compressed_eval<W, PV>(Bl, Bil, col, s, lc, nw, lane, mlist, rows, rins, joins, nodes, cnt, 0, 1);
+      else if (lc == 3)
+        tc = level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], nw, lane, vlist, joins, nodes, cnt, 0, 1);
+      else {
+        uint64_t j = 0;
+        uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], nw, lane, j, cnt, 0, 1);
+        joins += (lane == 0) ? j : 0;
+        tc = (lane == 0) ? t2 : 0;
+      }
+      lane_acc += tc;
+      if (PV) {
+        const uint64_t T = kc_wave_sum_u64(tc);
+        if (lane == 0) {
+          tot[d] += T;
+          if (T) atomicAdd(&cnt[x], (unsigned long long)T);
+        }
+        kc_wave_lds_sync();
+      }
+    } else {
+      if (lane == 0) {
+        chosen[d] = x;
+        cur[d + 1] = firstpos[lc];
+        tot[d + 1] = 0;
+      }
+      if (lane < W) stk[(d + 1) * W + lane] = nw;
+      kc_wave_lds_sync();
+      d++;
+    }
+  }
+  return lane_acc;
+}
+
+template <int W, int NW, bool PV, bool COMP>
 __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
-  using LY = ListLayout<W, NW, PV>;
+  using LY = ListLayout<W, NW, PV, COMP>;
+  const int K = a.k + 1;
   constexpr int S = LY::S;
   constexpr int SP = LY::SP;
   extern __shared__ uint32_t lds[];
@@ -653,23 +792,23 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   uint32_t* col = lds + LY::oCol;
   int32_t* firstpos = (int32_t*)(lds + LY::oFirst);
   uint32_t* C0 = lds + LY::oC0;
-  int32_t* sh = (int32_t*)(lds + LY::oSh);  // [0] task lo, [1] task hi, [2] child cursor
+  int32_t* sh = (int32_t*)(lds + LY::oSh);  // [0] task lo, [1] task hi
   unsigned long long* shtot = (unsigned long long*)(lds + LY::oSh + 8);
-  unsigned long long* cnt = (unsigned long long*)(lds + LY::oCnt);
+  unsigned long long* cnt = (unsigned long long*)(lds + LY::oCnt(K));
 
   const int tid = threadIdx.x;
   const int wid = tid >> 6;
   const int lane = tid & 63;
-  uint32_t* wblk = lds + LY::oWave + wid * LY::wave_words;
+  uint32_t* wblk = lds + LY::oWave + wid * LY::wave_words(K);
   unsigned long long* tot = (unsigned long long*)wblk;
-  int32_t* cur = (int32_t*)(wblk + 2 * (KC_KMAX + 1));
-  int32_t* chosen = cur + (KC_KMAX + 1);
-  uint32_t* stk = (uint32_t*)(chosen + (KC_KMAX + 1));
-  uint16_t* xlist = (uint16_t*)(stk + (KC_KMAX + 1) * W);
-  uint16_t* vlist = xlist + S;
-  uint32_t* pairs = (uint32_t*)(vlist + S);
+  uint64_t* rows = (uint64_t*)(wblk + 2 * K);
+  uint64_t* rins = rows + 64;
+  int32_t* cur = (int32_t*)(wblk + 2 * K + (COMP ? 256 + 24 : 0));
+  int32_t* chosen = cur + K;
+  uint32_t* stk = (uint32_t*)(chosen + K);
+  uint16_t* mlist = (uint16_t*)(stk + K * W);
+  uint16_t* vlist = mlist + 64;
 
-  const int k = a.k;
   uint64_t my_nodes = 0, my_isect = 0;  // per lane
 
   for (;;) {
@@ -692,6 +831,7 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       const int Wc = d_wclass_words(a.ri.cls[r]);
       const int Sr = 32 * Wc;
       const int64_t bo = a.ri.boff[r], po = a.ri.poff[r];
+      const int k = kc_vk(a.vk, a.roots[r], a.k);
       // stage the root's bitmaps into LDS
       for (int w = 0; w < W; ++w)
         for (int p = tid; p < S; p += 64 * NW) {
@@ -704,8 +844,8 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
         if (PV) cnt[p] = 0;
       }
       if (tid == 0) {
-        sh[2] = 0;
         shtot[0] = 0;
+        sh[2] = 0;
       }
       __syncthreads();
       // firstpos[c] = number of positions with color < c (colors ascend)
@@ -732,114 +872,11 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       if (v1 >= 0) L0--;
       if (v2 >= 0) L0--;
       __syncthreads();
-      const int first2 = firstpos[2], first3 = firstpos[3];
       if (wid == 0) my_nodes += (lane == 0);
-      uint64_t wave_total = 0;  // per lane
       const uint32_t c0w = lane < W ? C0[lane] : 0u;
-      if (L0 == 2) {
-        // the task node is a level-2 node: its 64-position chunks are dealt
-        // round-robin to the waves
-        uint64_t j = 0;
-        uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, first2, c0w, lane, j, cnt, wid, NW);
-        wave_total += (lane == 0) ? t2 : 0;
-        my_isect += (lane == 0) ? j : 0;
-      } else if (L0 == 3) {
-        wave_total += level3_eval<W, PV>(Bl, Bil, s, first2, first3, c0w, lane, vlist, my_isect, my_nodes, cnt, wid,
-                                         NW);
-      } else if (L0 == 4) {
-        wave_total += level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], c0w, lane, xlist, vlist, pairs,
-                                         LY::PCAP, my_isect, my_nodes, cnt, wid, NW);
-      } else {
-        // children of the task node are handed out to waves
-        int limit = 0;
-        {
-          int hiw = kc_wave_max_i32((lane < W && c0w) ? lane : -1);
-          if (hiw >= 0) limit = hiw * 32 + 32 - __clz((int)kc_readlane(c0w, hiw));
-        }
-        for (;;) {
-          int v = -1;
-          if (lane == 0) {
-            for (;;) {
-              int p = atomicAdd(&sh[2], 1) + firstpos[L0];
-              if (p >= limit) { v = -1; break; }
-              if ((C0[p >> 5] >> (p & 31)) & 1u) { v = p; break; }
-            }
-          }
-          v = __shfl(v, 0, 64);
-          if (v < 0) break;
-          // BitJoin at the task level
-          const uint32_t cw = lane < W ? (Bl[lane * SP + v] & c0w) : 0u;
-          my_isect += (lane == 0);
-          const uint32_t pc = split_popc(cw);
-          if ((int)pc < L0 - 1) continue;
-          my_nodes += (lane == 0);
-          uint64_t sub = 0;  // per lane share of the child's leaves
-          if (L0 - 1 == 4) {
-            sub = level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], cw, lane, xlist, vlist, pairs, LY::PCAP,
-                                     my_isect, my_nodes, cnt, 0, 1);
-          } else {
-            // depth-first from (L0-1, cw); nodes of level 4 are evaluated whole
-            if (lane < W) stk[lane] = cw;
-            int d = 0;
-            if (lane == 0) { cur[0] = firstpos[L0 - 1]; tot[0] = 0; }
-            kc_wave_lds_sync();
-            uint64_t lane_acc = 0;  // this lane's leaves below the child, credited per level
-            for (;;) {
-              const int l = L0 - 1 - d;
-              const uint32_t mw = lane < W ? stk[d * W + lane] : 0u;
-              const int from = cur[d];
-              const int x = split_next<W>(mw, from, lane);
-              if (x < 0) {
-                if (d == 0) break;
-                if (PV && lane == 0) {
-                  unsigned long long T = tot[d];
-                  tot[d - 1] += T;
-                  if (T) atomicAdd(&cnt[chosen[d - 1]], T);
-                }
-                kc_wave_lds_sync();
-                d--;
-                continue;
-              }
-              if (lane == 0) cur[d] = x + 1;
-              kc_wave_lds_sync();
-              const uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
-              my_isect += (lane == 0);
-              const uint32_t npc = split_popc(nw);
-              if ((int)npc < l - 1) continue;
-              my_nodes += (lane == 0);
-              if (l - 1 == 4) {
-                uint64_t t3 = level4_eval<W, PV>(Bl, Bil, s, first2, first3, firstpos[4], nw, lane, xlist, vlist,
-                                                 pairs, LY::PCAP, my_isect, my_nodes, cnt, 0, 1);
-                lane_acc += t3;
-                if (PV) {
-                  // the node total is needed for the chosen vertices above
-                  uint64_t T3 = kc_wave_sum_u64(t3);
-                  if (lane == 0) {
-                    tot[d] += T3;
-                    if (T3) atomicAdd(&cnt[x], (unsigned long long)T3);
-                  }
-                  kc_wave_lds_sync();
-                }
-              } else {
-                if (lane == 0) {
-                  chosen[d] = x;
-                  cur[d + 1] = firstpos[l - 1];
-                  tot[d + 1] = 0;
-                }
-                if (lane < W) stk[(d + 1) * W + lane] = nw;
-                kc_wave_lds_sync();
-                d++;
-              }
-            }
-            sub = lane_acc;
-          }
-          if (PV) {
-            uint64_t T = kc_wave_sum_u64(sub);
-            if (lane == 0 && T) atomicAdd(&cnt[v], (unsigned long long)T);
-          }
-          wave_total += sub;
-        }
-      }
+      const uint64_t wave_total = eval_node<W, PV, COMP>(Bl, Bil, col, firstpos, s, L0, c0w, lane, stk, cur, chosen, tot,
+                                                   mlist, rows, rins, vlist, my_isect, my_nodes, cnt, wid, NW,
+                                                   a.cmax, a.clev, &sh[2]);
       {
         const uint64_t wt = kc_wave_sum_u64(wave_total);
         if (lane == 0 && wt) atomicAdd(&shtot[0], (unsigned long long)wt);
@@ -850,6 +887,7 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       const int32_t u = a.roots[r];
       if (tid == 0 && T) {
         kc_add_checked(a.count, T, a.flags);
+        if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
         if (PV) {
           kc_add_checked(&a.pv[u], T, a.flags);
           if (v1 >= 0) kc_add_checked(&a.pv[a.perm[po + v1]], T, a.flags);
@@ -914,24 +952,34 @@ __device__ __forceinline__ float log_binom(float n, float k) {
 #define KC_LOGW_BINS 512
 #define KC_LOGW_SCALE 8.0f
 
-__global__ void k_sched_logw(int32_t R, int k, const int32_t* __restrict__ s, const float* __restrict__ pred,
-                             float* logw, int32_t* hist) {
+__global__ void k_sched_logw(int32_t R, int k, const int32_t* __restrict__ roots, const int32_t* vk,
+                             const int32_t* __restrict__ s, const int32_t* __restrict__ cls,
+                             const float* __restrict__ pred, float* logw, int32_t* hist) {
   int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
-  float lw = pred ? pred[r] : log_binom((float)s[r], (float)(k - 1));
+  const int kr = kc_vk(vk, roots[r], k);
+  float lw = pred ? pred[r] : log_binom((float)s[r], (float)(kr - 1));
   if (!(lw > -1e30f)) lw = 0.f;  // NaN guard
   logw[r] = lw;
   int b = (int)(lw * KC_LOGW_SCALE);
   b = b < 0 ? 0 : (b >= KC_LOGW_BINS ? KC_LOGW_BINS - 1 : b);
-  atomicAdd(&hist[b], 1);
+  atomicAdd(&hist[cls[r] * KC_LOGW_BINS + b], 1);  // one histogram per word class
 }
+
+struct ClassBins {
+  int lo[KC_NCLASS];
+  int hi[KC_NCLASS];
+};
 
 // depth 2 above `hi`, depth 1 above `lo` (bin units); a split must leave a
 // node of level >= 2 below it.
-__global__ void k_sched_depth(int32_t R, int k, const float* __restrict__ logw, int lo_bin, int hi_bin, int force,
-                              int32_t* depth) {
+__global__ void k_sched_depth(int32_t R, int k0, const int32_t* __restrict__ roots, const int32_t* vk,
+                              const int32_t* __restrict__ cls, const float* __restrict__ logw, ClassBins cb,
+                              int force, int32_t* depth) {
   int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int k = kc_vk(vk, roots[r], k0);
+  const int lo_bin = cb.lo[cls[r]], hi_bin = cb.hi[cls[r]];
   int b = (int)(logw[r] * KC_LOGW_SCALE);
   int d = 0;
   if (force >= 0) {
@@ -956,6 +1004,7 @@ struct SplitArgs {
   const int32_t* depth;
   const float* logw;
   int k;
+  const int32_t* vk;
   uint64_t* tasks;
   int32_t* task_bin;
   unsigned long long* ntasks;
@@ -976,7 +1025,7 @@ __global__ __launch_bounds__(64) void k_bitcol_split(SplitArgs a, const int32_t*
     const int Sr = 32 * Wc;
     const uint32_t* Br = a.B + a.ri.boff[r];
     const uint16_t* colr = a.color + a.ri.poff[r];
-    const int k = a.k;
+    const int k = kc_vk(a.vk, a.roots[r], a.k);
     uint64_t nodes = 1, isect = 0;  // the top call
     for (int p0 = 0; p0 < s; p0 += 64) {
       const int v1 = p0 + lane;
@@ -1106,9 +1155,9 @@ __global__ void k_add_counters(const unsigned long long* __restrict__ per_class,
 // ============================================================== host side
 template <int W, int NW, bool PV>
 static int launch_list(const ListArgs& a, hipStream_t st) {
-  using LY = ListLayout<W, NW, PV>;
-  const size_t bytes = LY::bytes();
-  auto fn = k_bitcol_list<W, NW, PV>;
+  const bool comp = a.cmax > 0;
+  const size_t bytes = comp ? ListLayout<W, NW, PV, true>::bytes(a.k + 1) : ListLayout<W, NW, PV, false>::bytes(a.k + 1);
+  auto fn = comp ? k_bitcol_list<W, NW, PV, true> : k_bitcol_list<W, NW, PV, false>;
   KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   int per_cu = 0;
   KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * NW, bytes));
@@ -1123,8 +1172,8 @@ static int launch_list(const ListArgs& a, hipStream_t st) {
 
 template <int W, bool PV>
 static int launch_list_nw(const ListArgs& a, int nw, hipStream_t st) {
-  if (nw >= 4) return launch_list<W, 4, PV>(a, st);
-  if (nw == 2) return launch_list<W, 2, PV>(a, st);
+  if (nw >= 8) return launch_list<W, 8, PV>(a, st);
+  if (nw >= 2) return launch_list<W, 4, PV>(a, st);
   return launch_list<W, 1, PV>(a, st);
 }
 
@@ -1266,44 +1315,51 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     KC_HIP(hipGetLastError());
     KC_TRY(kc_mlp_forward_dev(opt->mlp_params, x, R, pred, st));
   }
+  // Split thresholds are set per word class: each class is its own
+  // persistent launch, so each has its own tail to keep short.
   int32_t* hist;
-  KC_TRY(scr.get(&hist, KC_LOGW_BINS));
-  KC_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * KC_LOGW_BINS, st));
-  k_sched_logw<<<(R + 255) / 256, 256, 0, st>>>(R, c.k, ri.s, pred, logw, hist);
+  KC_TRY(scr.get(&hist, KC_NCLASS * KC_LOGW_BINS));
+  KC_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * KC_NCLASS * KC_LOGW_BINS, st));
+  k_sched_logw<<<(R + 255) / 256, 256, 0, st>>>(R, c.k, c.roots, c.vk, ri.s, ri.cls, pred, logw, hist);
   KC_HIP(hipGetLastError());
-  std::vector<int32_t> hh(KC_LOGW_BINS);
-  KC_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * KC_LOGW_BINS, hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> hh(KC_NCLASS * KC_LOGW_BINS);
+  KC_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * hh.size(), hipMemcpyDeviceToHost, st));
   KC_HIP(hipStreamSynchronize(st));
-  // split thresholds, in histogram bins
   const int slots = kc_device_cus() * 4;
-  int lo_bin = KC_LOGW_BINS, hi_bin = KC_LOGW_BINS;
-  if (opt && opt->split_threshold > 0.f) {
-    lo_bin = (int)(opt->split_threshold * KC_LOGW_SCALE);
-    hi_bin = (int)((opt->split_threshold + 4.0f) * KC_LOGW_SCALE);
-  } else if (learned) {
-    // predicted total work; a root heavier than 1/(8 slots) of it is split
-    // once, and one heavier than 64 such shares twice
-    double tot = 0.0;
-    for (int b = 0; b < KC_LOGW_BINS; ++b) tot += (double)hh[b] * exp((b + 0.5) / KC_LOGW_SCALE);
-    double target = tot / (8.0 * slots);
-    if (target > 1.0) {
-      lo_bin = (int)(log(target) * KC_LOGW_SCALE) + 1;
-      hi_bin = (int)(log(target * 64.0) * KC_LOGW_SCALE) + 1;
+  ClassBins cb;
+  for (int cl = 0; cl < KC_NCLASS; ++cl) {
+    const int32_t* h = hh.data() + cl * KC_LOGW_BINS;
+    int lo_bin = KC_LOGW_BINS, hi_bin = KC_LOGW_BINS;
+    if (opt && opt->split_threshold > 0.f) {
+      lo_bin = (int)(opt->split_threshold * KC_LOGW_SCALE);
+      hi_bin = (int)((opt->split_threshold + 4.0f) * KC_LOGW_SCALE);
+    } else if (learned) {
+      // the class's predicted work; a root heavier than 1/(8 slots) of it is
+      // split once, one heavier than 64 such shares twice
+      double tot = 0.0;
+      for (int b = 0; b < KC_LOGW_BINS; ++b) tot += (double)h[b] * exp((b + 0.5) / KC_LOGW_SCALE);
+      double target = tot / (8.0 * slots);
+      if (target > 1.0) {
+        lo_bin = (int)(log(target) * KC_LOGW_SCALE) + 1;
+        hi_bin = (int)(log(target * 64.0) * KC_LOGW_SCALE) + 1;
+      }
+    } else {
+      // degree schedule: in each class the slots/4 roots of largest d+ are
+      // split twice and the next 4 x slots once
+      const int64_t n2 = slots / 4, n1 = (int64_t)slots * 4;
+      int64_t cum = 0;
+      for (int b = KC_LOGW_BINS - 1; b >= 0; --b) {
+        cum += h[b];
+        if (hi_bin == KC_LOGW_BINS && cum >= n2) hi_bin = b + 1;
+        if (cum >= n2 + n1) { lo_bin = b + 1; break; }
+      }
+      if (lo_bin > hi_bin) lo_bin = hi_bin;
     }
-  } else {
-    // degree schedule: the slots/4 roots of largest d+ are split twice, the
-    // next 4 x slots once
-    const int64_t n2 = slots / 4, n1 = (int64_t)slots * 4;
-    int64_t cum = 0;
-    for (int b = KC_LOGW_BINS - 1; b >= 0; --b) {
-      cum += hh[b];
-      if (hi_bin == KC_LOGW_BINS && cum >= n2) hi_bin = b + 1;
-      if (cum >= n2 + n1) { lo_bin = b + 1; break; }
-    }
-    if (lo_bin > hi_bin) lo_bin = hi_bin;
+    cb.lo[cl] = lo_bin;
+    cb.hi[cl] = hi_bin;
   }
   const int force = opt ? opt->split : 0;
-  k_sched_depth<<<(R + 255) / 256, 256, 0, st>>>(R, c.k, logw, lo_bin, hi_bin, force, depth);
+  k_sched_depth<<<(R + 255) / 256, 256, 0, st>>>(R, c.k, c.roots, c.vk, ri.cls, logw, cb, force, depth);
   KC_HIP(hipGetLastError());
   // roots to split
   int32_t *splitlist, *nsplit;
@@ -1323,6 +1379,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   sp.depth = depth;
   sp.logw = logw;
   sp.k = c.k;
+  sp.vk = c.vk;
   sp.root_isect = c.root_isect;
   sp.root_work = c.root_work;
   sp.counters = c.counters;
@@ -1380,11 +1437,30 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   unsigned long long* cls_ctr;
   KC_TRY(scr.get(&cls_ctr, 3 * KC_NCLASS));
   KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * 3 * KC_NCLASS, st));
+  // The classes' persistent kernels run concurrently on their own streams
+  // (default priority) so that one class's tail overlaps the next class's work.
+  struct Streams {
+    hipStream_t s[KC_NCLASS] = {};
+    hipEvent_t done[KC_NCLASS] = {};
+    ~Streams() {
+      for (int i = 0; i < KC_NCLASS; ++i) {
+        if (done[i]) (void)hipEventDestroy(done[i]);
+        if (s[i]) (void)hipStreamDestroy(s[i]);
+      }
+    }
+  } cs;
+  hipEvent_t ready;
+  KC_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  struct EvGuard { hipEvent_t e; ~EvGuard() { (void)hipEventDestroy(e); } } ready_guard{ready};
+  KC_HIP(hipEventRecord(ready, st));
   for (int cl = KC_NCLASS - 1; cl >= 0; --cl) {
     int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
     if (hi <= lo) continue;
+    KC_HIP(hipStreamCreateWithFlags(&cs.s[cl], hipStreamNonBlocking));
+    KC_HIP(hipEventCreateWithFlags(&cs.done[cl], hipEventDisableTiming));
+    KC_HIP(hipStreamWaitEvent(cs.s[cl], ready, 0));
     KC_TRY(ev_cls[cl].init());
-    KC_HIP(hipEventRecord(ev_cls[cl].a, st));
+    KC_HIP(hipEventRecord(ev_cls[cl].a, cs.s[cl]));
     ListArgs la;
     la.roots = c.roots;
     la.ri = ri;
@@ -1399,14 +1475,20 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     int chunk = opt && opt->chunk > 0 ? opt->chunk : (kWClass[cl] >= 8 ? 1 : 8);
     la.chunk = chunk;
     la.k = c.k;
+    la.vk = c.vk;
+    la.root_count = c.root_count;
+    la.cmax = opt && opt->compress > 0 ? (opt->compress > 64 ? 64 : opt->compress) : 0;
+    la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
     la.count = c.count;
     la.pv = c.pv;
     la.counters = cls_ctr + 3 * cl;
     la.root_work = c.root_work;
     la.root_isect = c.root_isect;
     la.flags = c.flags;
-    KC_TRY(launch_list_class(la, cl, nw, pv, st));
-    KC_HIP(hipEventRecord(ev_cls[cl].b, st));
+    KC_TRY(launch_list_class(la, cl, nw, pv, cs.s[cl]));
+    KC_HIP(hipEventRecord(ev_cls[cl].b, cs.s[cl]));
+    KC_HIP(hipEventRecord(cs.done[cl], cs.s[cl]));
+    KC_HIP(hipStreamWaitEvent(st, cs.done[cl], 0));
     launches++;
   }
   k_add_counters<<<1, 64, 0, st>>>(cls_ctr, KC_NCLASS, c.counters);

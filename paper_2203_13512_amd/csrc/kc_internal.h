@@ -147,13 +147,16 @@ struct kc_prep_out {
   int32_t max_core;
 };
 int kc_validate_graph(const kc_dev_graph& g, int* flags_dev, hipStream_t s);
-int kc_preprocess(const kc_dev_graph& g, int32_t k, int32_t order, unsigned long long* prelist_count_dev,
-                  unsigned long long* pv_dev, int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s);
+int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
+                  unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
+                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s);
 
 // Listing (kc_sdegree.hip, kc_bitcol.hip).
 struct kc_list_ctx {
   int32_t n;
-  int32_t k;
+  int32_t k;               // maximum k
+  const int32_t* vk;       // per-vertex k (nullable: uniform k)
+  unsigned long long* root_count;  // per-vertex attribution (nullable)
   const int32_t* drp;
   const int32_t* dcol;
   const int32_t* core;
@@ -183,6 +186,8 @@ int kc_mlp_forward_dev(const float* params, const float* x, int32_t rows, float*
 int kc_bin_sort(const int32_t* bin_dev, int32_t n, int32_t nbins, int32_t* out_dev, int32_t* host_off,
                 kc_scratch& scr, hipStream_t s);
 int kc_device_cus();
+__device__ __forceinline__ int kc_vk(const int32_t* vk, int32_t v, int k) { return vk ? vk[v] : k; }
+
 // Quantised schedule key (0..63, larger = heavier) from a work estimate in
 // natural-log units.
 __device__ __forceinline__ int kc_key_q(float logw) {

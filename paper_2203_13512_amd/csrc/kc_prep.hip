@@ -175,13 +175,13 @@ int kc_validate_graph(const kc_dev_graph& g, int* flags_dev, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- Pre-Core
-__global__ void k_precore_init(int32_t n, const int32_t* __restrict__ rp, int32_t km1, int32_t* deg,
-                               uint8_t* removed, int32_t* F, int32_t* fcount) {
+__global__ void k_precore_init(int32_t n, const int32_t* __restrict__ rp, int32_t km1, const int32_t* vk,
+                               int32_t* deg, uint8_t* removed, int32_t* F, int32_t* fcount) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int32_t d = rp[v + 1] - rp[v];
   deg[v] = d;
-  bool rm = d < km1;
+  bool rm = d < kc_vk(vk, v, km1 + 1) - 1;
   removed[v] = rm ? 1 : 0;
   if (rm) F[atomicAdd(fcount, 1)] = v;
 }
@@ -189,8 +189,8 @@ __global__ void k_precore_init(int32_t n, const int32_t* __restrict__ rp, int32_
 // One wave per frontier vertex; every neighbour's degree drops by one and the
 // decrement that crosses from km1 to km1-1 enqueues it.
 __global__ void k_precore_peel(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t km1,
-                               const int32_t* __restrict__ F, int32_t nf, int32_t* deg, uint8_t* removed,
-                               int32_t* Fnext, int32_t* fnext_count) {
+                               const int32_t* vk, const int32_t* __restrict__ F, int32_t nf, int32_t* deg,
+                               uint8_t* removed, int32_t* Fnext, int32_t* fnext_count) {
   int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / KC_WAVE;
   if (wave >= nf) return;
   int lane = kc_lane();
@@ -198,7 +198,7 @@ __global__ void k_precore_peel(const int32_t* __restrict__ rp, const int32_t* __
   for (int32_t i = rp[u] + lane; i < rp[u + 1]; i += KC_WAVE) {
     int32_t v = col[i];
     int32_t old = atomicSub(&deg[v], 1);
-    if (old == km1) {
+    if (old == kc_vk(vk, v, km1 + 1) - 1) {
       removed[v] = 1;
       Fnext[atomicAdd(fnext_count, 1)] = v;
     }
@@ -252,9 +252,10 @@ __global__ void k_uf_stats(int32_t n, const uint8_t* removed, int32_t* parent, c
 
 // A live root whose component's degree sum is n_c (n_c - 1) is a clique
 // component: it contributes C(n_c, k) cliques.
-__global__ void k_prelist_roots(int32_t n, int32_t k, const uint8_t* removed, const int32_t* parent,
-                                const int32_t* comp_n, const unsigned long long* comp_dsum, uint8_t* is_clique,
-                                unsigned long long* prelist_count, int* flags) {
+__global__ void k_prelist_roots(int32_t n, int32_t k, const int32_t* vk, const uint8_t* removed,
+                                const int32_t* parent, const int32_t* comp_n, const unsigned long long* comp_dsum,
+                                uint8_t* is_clique, unsigned long long* prelist_count,
+                                unsigned long long* root_count, int* flags) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   is_clique[v] = 0;
@@ -263,13 +264,14 @@ __global__ void k_prelist_roots(int32_t n, int32_t k, const uint8_t* removed, co
   if (comp_dsum[v] != nc * (nc - 1)) return;
   is_clique[v] = 1;
   uint64_t c;
-  if (!kc_binom(nc, (uint64_t)k, &c)) { atomicOr(flags, KC_FLAG_OVERFLOW); return; }
+  if (!kc_binom(nc, (uint64_t)kc_vk(vk, v, k), &c)) { atomicOr(flags, KC_FLAG_OVERFLOW); return; }
   kc_add_checked(prelist_count, c, flags);
+  if (root_count) kc_add_checked(&root_count[v], c, flags);  // v is the component's smallest vertex
 }
 
-__global__ void k_prelist_remove(int32_t n, int32_t k, uint8_t* removed, const int32_t* parent,
-                                 const int32_t* comp_n, const uint8_t* is_clique, unsigned long long* pv,
-                                 int* flags) {
+__global__ void k_prelist_remove(int32_t n, int32_t k, const int32_t* vk, uint8_t* removed,
+                                 const int32_t* parent, const int32_t* comp_n, const uint8_t* is_clique,
+                                 unsigned long long* pv, int* flags) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || removed[v]) return;
   int32_t r = parent[v];
@@ -277,7 +279,10 @@ __global__ void k_prelist_remove(int32_t n, int32_t k, uint8_t* removed, const i
   removed[v] = 1;
   if (pv) {
     uint64_t c;
-    if (!kc_binom((uint64_t)comp_n[r] - 1, (uint64_t)k - 1, &c)) { atomicOr(flags, KC_FLAG_OVERFLOW); return; }
+    if (!kc_binom((uint64_t)comp_n[r] - 1, (uint64_t)kc_vk(vk, v, k) - 1, &c)) {
+      atomicOr(flags, KC_FLAG_OVERFLOW);
+      return;
+    }
     kc_add_checked(&pv[v], c, flags);
   }
 }
@@ -424,8 +429,9 @@ static int read_i32(const int32_t* dev, int32_t* host, hipStream_t s) {
   return KC_OK;
 }
 
-int kc_preprocess(const kc_dev_graph& g, int32_t k, int32_t order, unsigned long long* prelist_count_dev,
-                  unsigned long long* pv_dev, int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s) {
+int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
+                  unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
+                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s) {
   const int32_t n = g.n;
   const int32_t km1 = k - 1;
   memset(out, 0, sizeof(*out));
@@ -444,15 +450,15 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, int32_t order, unsigned long
   // ---- Pre-Core (Alg. 3)
   KC_HIP(hipMemsetAsync(counters, 0, 8 * sizeof(int32_t), s));
   if (n > 0) {
-    k_precore_init<<<grid_for(n), 256, 0, s>>>(n, g.rp, km1, out->deg, out->removed, F0, counters);
+    k_precore_init<<<grid_for(n), 256, 0, s>>>(n, g.rp, km1, vk, out->deg, out->removed, F0, counters);
     KC_HIP(hipGetLastError());
   }
   KC_TRY(read_i32(counters, hcnt, s));
   int32_t nf = hcnt[0];
   while (nf > 0) {
     KC_HIP(hipMemsetAsync(counters + 1, 0, sizeof(int32_t), s));
-    k_precore_peel<<<grid_for((int64_t)nf * KC_WAVE), 256, 0, s>>>(g.rp, g.col, km1, F0, nf, out->deg, out->removed,
-                                                                    F1, counters + 1);
+    k_precore_peel<<<grid_for((int64_t)nf * KC_WAVE), 256, 0, s>>>(g.rp, g.col, km1, vk, F0, nf, out->deg,
+                                                                    out->removed, F1, counters + 1);
     KC_HIP(hipGetLastError());
     KC_TRY(read_i32(counters + 1, hcnt, s));
     nf = hcnt[0];
@@ -474,9 +480,10 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, int32_t order, unsigned long
       k_uf_init<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent);
       k_uf_hook<<<grid_for((int64_t)n * KC_WAVE), 256, 0, s>>>(n, g.rp, g.col, out->removed, parent);
       k_uf_stats<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, out->deg, comp_n, comp_dsum);
-      k_prelist_roots<<<grid_for(n), 256, 0, s>>>(n, k, out->removed, parent, comp_n, comp_dsum, is_clique,
-                                                   prelist_count_dev, flags_dev);
-      k_prelist_remove<<<grid_for(n), 256, 0, s>>>(n, k, out->removed, parent, comp_n, is_clique, pv_dev, flags_dev);
+      k_prelist_roots<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, comp_dsum, is_clique,
+                                                   prelist_count_dev, root_count, flags_dev);
+      k_prelist_remove<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, is_clique, pv_dev,
+                                                    flags_dev);
       KC_HIP(hipGetLastError());
     }
   }

@@ -43,7 +43,9 @@ struct SdArgs {
   int32_t ntasks;
   unsigned long long* head;
   int chunk;
-  int k;
+  int k;                  // maximum k (memory layout)
+  const int32_t* vk;      // per-vertex k (nullable)
+  unsigned long long* root_count;
   int SMAX;
   uint32_t* gscratch;     // per-workgroup memory when the lists do not fit LDS
   size_t block_words;
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
       const int32_t u = a.roots[r];
       const int32_t b0 = a.drp[u];
       const int32_t s0 = a.drp[u + 1] - b0;
+      const int kt = kc_vk(a.vk, u, a.k);
       for (int i = lane; i < s0; i += 64) {
         list[i] = a.dcol[b0 + i];
         if (PV) {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
       }
       __syncthreads();
       my_nodes++;
-      const int L0 = K - 1;
+      const int L0 = kt - 1;
       int d = 0;
       for (;;) {
         const int l = L0 - d;
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
       const unsigned long long T = tot[0];
       if (lane == 0 && T) {
         kc_add_checked(a.count, T, a.flags);
+        if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
         if (PV) kc_add_checked(&a.pv[u], T, a.flags);
       }
       if (PV)
@@ -227,11 +231,12 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   }
 }
 
-__global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp, int k,
-                          int32_t* bin, int* flags) {
+__global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp, int k0,
+                          const int32_t* vk, int32_t* bin, int* flags) {
   int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   int32_t u = roots[r];
+  const int k = kc_vk(vk, u, k0);
   int s = drp[u + 1] - drp[u];
   int c = sd_class_of(s);
   if (c < 0) {
@@ -260,7 +265,7 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   int32_t *bin, *order;
   KC_TRY(scr.get(&bin, R));
   KC_TRY(scr.get(&order, R));
-  k_sd_bins<<<(R + 255) / 256, 256, 0, st>>>(R, c.roots, c.drp, c.k, bin, c.flags);
+  k_sd_bins<<<(R + 255) / 256, 256, 0, st>>>(R, c.roots, c.drp, c.k, c.vk, bin, c.flags);
   KC_HIP(hipGetLastError());
   const int NB = SD_NCLASS * 64;
   std::vector<int32_t> boff(NB + 1);
@@ -296,6 +301,8 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     a.head = heads + cl;
     a.chunk = c.opt && c.opt->chunk > 0 ? c.opt->chunk : (cl <= 1 ? 8 : 1);
     a.k = c.k;
+    a.vk = c.vk;
+    a.root_count = c.root_count;
     a.SMAX = kSClass[cl];
     a.count = c.count;
     a.pv = c.pv;

@@ -247,8 +247,35 @@ def test_scaled_workloads(cfg, scale, ks):
 
 
 def test_batched_counts_equal_single_runs():
+    """Many graphs with their own k in one call (one union graph, one listing
+    launch per word class) equal the oracle graph by graph."""
     w = graphgen.workload(4, scale=0.03)
-    say("batched", w.name, len(w.graphs))
-    got = kc.count_batched(w.graphs, w.ks, "color")
-    for (g, k), c in zip(zip(w.graphs, w.ks), got):
-        assert c == oracle.count(*g, k)
+    ks = list(w.ks)
+    ks[0], ks[1] = 1, 2  # the linear cases ride along
+    for order in ORDERS:
+        say("batched", w.name, len(w.graphs), order)
+        got = kc.count_batched(w.graphs, ks, order)
+        for (g, k), c in zip(zip(w.graphs, ks), got):
+            assert c == oracle.count(*g, k), (k, order)
+
+
+def test_root_attribution_sums_to_the_total():
+    g = graphgen.chung_lu(4000, 12.0, 2.1, 400.0, planted=[20, 12], seed=21)
+    g = G.disjoint_union([g, G.complete(9), G.complete(5)])
+    for order in ORDERS:
+        for k in (3, 5, 7):
+            say("root attribution", order, k)
+            rp, ci = dev(g)
+            rc = torch.zeros(len(g[0]) - 1, dtype=torch.int64, device="cuda")
+            opt = kc.Options()
+            kc._lib().kc_options_init(kc.ctypes.byref(opt))
+            opt.device_ptrs = 1
+            opt.stream = kc._torch_stream(rp.device)
+            opt.root_count = rc.data_ptr()
+            out = kc.ctypes.c_uint64(0)
+            st = kc._lib().kclique_count_ex(len(g[0]) - 1, rp.data_ptr(), ci.data_ptr(), k, kc.ORDERS[order],
+                                            kc.ctypes.byref(opt), kc.ctypes.byref(out), None)
+            assert st == 0
+            want = oracle.count(*g, k)
+            assert out.value == want
+            assert int(rc.sum().item()) == want
