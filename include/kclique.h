@@ -80,6 +80,8 @@ typedef struct {
   uint64_t work;          /* SDegree: sum of |C|+d+ per join; BitCol: sum of ceil(s/32) words per BitJoin */
   uint64_t staged_words;  /* BitCol: 32-bit words of encoded bitmaps written */
   uint64_t stage_bytes;   /* BitCol: algorithmic bytes read while staging: 4*(d+_u + sum of d+_v) */
+  uint64_t isect_wide;    /* BitCol: of `isect`, BitJoins done as one whole-wave step on full-width bitmaps */
+  uint64_t isect_compressed; /* BitCol: of `isect`, BitJoins on re-encoded 64-bit rows (see `compress`) */
   /* per listing launch (BitCol: bitmap word class 1,2,4,8,12,16,24,32; SDegree: candidate-list class) */
   double class_ms[8];     /* device time of that class's persistent listing kernel */
   uint64_t class_work[8]; /* its work, as `work` above */

@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
         ("n_roots", ctypes.c_int32), ("n_tasks", ctypes.c_int64), ("max_out_degree", ctypes.c_int32),
         ("max_core", ctypes.c_int32), ("prelist_count", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
         ("isect", ctypes.c_uint64), ("work", ctypes.c_uint64), ("staged_words", ctypes.c_uint64),
-        ("stage_bytes", ctypes.c_uint64), ("class_ms", ctypes.c_double * 8), ("class_work", ctypes.c_uint64 * 8),
+        ("stage_bytes", ctypes.c_uint64), ("isect_wide", ctypes.c_uint64), ("isect_compressed", ctypes.c_uint64),
+        ("class_ms", ctypes.c_double * 8), ("class_work", ctypes.c_uint64 * 8),
         ("class_tasks", ctypes.c_int64 * 8),
     ]
 

@@ -222,6 +222,8 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     stats->isect = hcnt[1];
     stats->work = hcnt[2];
     stats->stage_bytes = hcnt[3];
+    stats->isect_wide = hcnt[4];
+    stats->isect_compressed = hcnt[5];
   }
   return KC_OK;
 }

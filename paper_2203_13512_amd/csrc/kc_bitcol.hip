@@ -321,7 +321,7 @@ struct ListArgs {
   int clev;   // ... at nodes of level >= clev
   unsigned long long* count;
   unsigned long long* pv;
-  unsigned long long* counters;  // nodes, isect, work
+  unsigned long long* counters;  // nodes, isect, work, wave-wide joins, joins on re-encoded rows
   uint64_t* root_work;
   uint64_t* root_isect;
   int* flags;
@@ -331,8 +331,9 @@ struct ListArgs {
 // fields on even offsets):
 //   B[W][S+1] | Bin[W][S+1] (per-vertex) | color[S] | firstpos[KMAX+2] |
 //   C0[W] | shared scalars[16] | NW wave blocks | cnt[S] u64 (per-vertex)
-// A wave block holds tot[KMAX+1] u64 | cur[KMAX+1] | chosen[KMAX+1] |
-// rows/rins[64] u64 | stack[(KMAX+1)][W] | member list[64] u16 | candidate list[S] u16.
+// A wave block (sized for K = k+1 levels at run time) holds tot[K] u64 |
+// (compressed variant) rows[64], rins or the level-2 queue[128], cm[12] u64 |
+// cur[K] | chosen[K] | stack[K][W] | member list[64] u16 | candidate list[S] u16.
 #define KC_KMAX 32
 
 template <int W, int NW, bool PV, bool COMP>
@@ -348,10 +349,11 @@ struct ListLayout {
   static constexpr int oSh = a2(oC0 + W);
   static constexpr int oWave = oSh + 16;
   // per wave, for recursion depth K = k + 1 (runtime):
-  //   tot[K] u64 | [rows[64] rins[64] cm[12] u64 (compressed variant)] |
+  //   tot[K] u64 | [rows[64] rins[128] cm[12] u64 (compressed variant; when
+  //   counting, rins holds the queue of level-2 nodes)] |
   //   cur[K] | chosen[K] | stack[K][W] | mlist[64] u16 | vlist[S] u16
   __host__ __device__ static constexpr int wave_words(int K) {
-    return a2(2 * K + (COMP ? 256 + 24 : 0) + 2 * K + K * W + 32 + S / 2);
+    return a2(2 * K + (COMP ? 2 * (64 + 128 + 12) : 0) + 2 * K + K * W + 32 + S / 2);
   }
   __host__ __device__ static constexpr int oCnt(int K) { return oWave + NW * wave_words(K); }
   __host__ __device__ static constexpr int words(int K) { return oCnt(K) + (PV ? 2 * S : 0); }
@@ -512,6 +514,7 @@ __device__ __forceinline__ uint64_t level3_eval(const uint32_t* __restrict__ Bl,
 // subtree with a depth-first walk whose levels are unrolled at compile time
 // (cdfs<L>), so the walk's sets stay in registers.
 #define KC_CMAX 10  // deepest level evaluated on compressed rows
+#define KC_QMAX 8   // deepest level evaluated through the level-2 queue (count mode)
 
 struct CNode {
   const uint64_t* rows;   // R_j (LDS)
@@ -559,6 +562,100 @@ __device__ __forceinline__ uint64_t cdfs(const uint64_t* __restrict__ rows, cons
       }
     }
     return t;
+  }
+}
+
+// ---- count-only evaluation of compressed nodes of level >= 4 -------------
+// Each lane holds its member's row R in registers.  The levels above 3 are
+// walked by the whole wave with wave-uniform sets (the scalar unit does the
+// set bookkeeping; a chosen member's row is read from its lane); at a level-3
+// node every lane z forms its child R_z & X at once, and the children that
+// qualify as level-2 nodes are appended to a per-wave queue in LDS.  Each time
+// the queue holds 64 nodes every lane evaluates one of them (its leaves are
+// the popcounts of the BitJoins at level 2), so the leaf work is spread over
+// all lanes however unbalanced the subtrees above are.  Same joins, same
+// pruning and same counts as the recursive form.
+
+// Leaves of a level-2 node X: over members y of X with color >= 2, the sum of
+// popcount(R_y & X).  R_y only holds members below y, so for y < 32 the high
+// word is zero and one 32-bit AND and popcount suffice.
+__device__ __forceinline__ uint32_t cleaf(const uint64_t* __restrict__ rows, uint64_t X, uint64_t c2) {
+  const uint32_t xl = (uint32_t)X, xh = (uint32_t)(X >> 32);
+  const uint64_t cand = X & c2;
+  uint32_t lo = (uint32_t)cand, hi = (uint32_t)(cand >> 32);
+  const uint32_t* r32 = (const uint32_t*)rows;
+  uint32_t acc = 0;
+  while (lo) {
+    const int y = __ffs((int)lo) - 1;
+    lo &= lo - 1;
+    acc += (uint32_t)__popc(r32[2 * y] & xl);
+  }
+  while (hi) {
+    const int y = __ffs((int)hi) + 31;
+    hi &= hi - 1;
+    const uint64_t r = rows[y];
+    acc += (uint32_t)__popc((uint32_t)r & xl) + (uint32_t)__popc((uint32_t)(r >> 32) & xh);
+  }
+  return acc;
+}
+
+struct CQueue {
+  const uint64_t* rows;  // R_j (LDS)
+  uint64_t* q;           // 128 pending level-2 nodes (LDS, per wave)
+  int n;                 // pending count (wave-uniform)
+  uint64_t c2, c3;       // members with color >= 2, >= 3
+  uint64_t acc;          // this lane's leaves
+};
+
+__device__ __forceinline__ void cq_eval(CQueue& Q, int lane, int cnt_lanes, uint64_t& joins) {
+  kc_wave_lds_sync();
+  if (lane < cnt_lanes) {
+    const uint64_t Y = Q.q[Q.n - cnt_lanes + lane];
+    joins += (uint64_t)__popcll(Y & Q.c2);
+    Q.acc += cleaf(Q.rows, Y, Q.c2);
+  }
+  Q.n -= cnt_lanes;
+  kc_wave_lds_sync();
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t readfirstlane64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int L>
+__device__ __forceinline__ void wdfs(CQueue& Q, const uint64_t* __restrict__ cm, uint64_t R, uint64_t X,
+                                     uint64_t top, int lane, uint64_t& joins, uint64_t& nodes) {
+  if constexpr (L == 3) {
+    // level-3 node: lane z is candidate z
+    const bool cand = ((X & Q.c3 & top) >> lane) & 1ull;
+    const uint64_t X2 = R & X;
+    joins += cand ? 1u : 0u;
+    const bool push = cand && __popcll(X2) >= 2;
+    nodes += push ? 1u : 0u;
+    const uint64_t pm = kc_ballot(push);
+    if (push) Q.q[Q.n + kc_mbcnt(pm)] = X2;
+    Q.n += __popcll(pm);
+    if (Q.n >= 64) cq_eval(Q, lane, 64, joins);
+  } else {
+    uint64_t cand = X & readfirstlane64(cm[L]) & top;
+    while (cand) {
+      const int y = __ffsll((long long)cand) - 1;
+      cand &= cand - 1;
+      const uint64_t X2 = readlane64(R, y) & X;
+      joins += (lane == 0);
+      if (__popcll(X2) >= L - 1) {
+        nodes += (lane == 0);
+        wdfs<L - 1>(Q, cm, R, X2, ~0ull, lane, joins, nodes);
+      }
+    }
   }
 }
 
@@ -620,7 +717,7 @@ __device__ __forceinline__ uint64_t compressed_eval(const uint32_t* __restrict__
   rows[lane] = R;
   if (PV) rins[lane] = Rin;
   const int cv = valid ? (int)col[v] : 0;
-  uint64_t* cmw = rows + 128;  // cm[0..KC_CMAX] after rows and rins
+  uint64_t* cmw = rows + 192;  // cm[0..KC_CMAX] after rows and rins
 #pragma unroll
   for (int c = 0; c <= KC_CMAX; ++c) {
     const uint64_t b = kc_ballot(valid && cv >= c);
@@ -634,6 +731,25 @@ __device__ __forceinline__ uint64_t compressed_eval(const uint32_t* __restrict__
   nd.mlist = mlist;
   nd.cm = cmw;
   kc_wave_lds_sync();
+  if (!PV && l >= 4 && l <= KC_QMAX) {
+    CQueue Q;
+    Q.rows = rows;
+    Q.q = rins;  // the in-rows are not used when counting; 128 entries
+    Q.n = 0;
+    Q.c2 = cm2;
+    Q.c3 = kc_ballot(valid && cv >= 3);
+    Q.acc = 0;
+    // this wave's share of the node's candidates: members j with j % nparts == part
+    uint64_t deal = 0;
+    for (int j = part; j < 64; j += nparts) deal |= 1ull << j;
+#define KC_WD(LL) \
+  case LL: wdfs<LL>(Q, cmw, R, cm0, deal, lane, joins, nodes); break;
+    switch (l) { KC_WD(4) KC_WD(5) KC_WD(6) KC_WD(7) KC_WD(8) }
+#undef KC_WD
+    if (Q.n > 0) cq_eval(Q, lane, Q.n, joins);
+    kc_wave_lds_sync();
+    return Q.acc;
+  }
   uint64_t t = 0;
   // this lane's candidate: member `lane` of the node, if dealt to this wave
   const bool mine = valid && ((lane % nparts) == part);
@@ -674,13 +790,18 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
                               uint32_t cw, int lane, uint32_t* __restrict__ stk, int32_t* __restrict__ cur,
                               int32_t* __restrict__ chosen, unsigned long long* __restrict__ tot,
                               uint16_t* __restrict__ mlist, uint64_t* __restrict__ rows, uint64_t* __restrict__ rins,
-                              uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes,
-                              unsigned long long* cnt, int part, int nparts, int cmax, int clev,
+                              uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes, uint64_t& wjoins,
+                              uint64_t& cjoins, unsigned long long* cnt, int part, int nparts, int cmax, int clev,
                               int32_t* __restrict__ shared_next) {
   constexpr int SP = 32 * W + 1;
   const uint32_t m = split_popc(cw);
-  if (COMP && (int)m <= cmax && L <= KC_CMAX && L >= clev)
-    return compressed_eval<W, PV>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt, part, nparts);
+  if (COMP && (int)m <= cmax && L <= KC_CMAX && L >= clev) {
+    const uint64_t j0 = joins;
+    const uint64_t t = compressed_eval<W, PV>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt,
+                                              part, nparts);
+    cjoins += joins - j0;
+    return t;
+  }
   if (L == 2) {
     uint64_t j = 0;
     uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], cw, lane, j, cnt, part, nparts);
@@ -740,6 +861,7 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
     kc_wave_lds_sync();
     const uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
     joins += (lane == 0);
+    wjoins += (lane == 0);
     const uint32_t npc = split_popc(nw);
     if ((int)npc < l - 1) continue;
     nodes += (lane == 0);
@@ -747,9 +869,11 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
     const bool comp = COMP && (int)npc <= cmax && lc <= KC_CMAX && lc >= clev;
     if (comp || lc <= 3) {
       uint64_t tc;
-      if (COMP && comp)
+      if (COMP && comp) {
+        const uint64_t j0 = joins;
         tc = compressed_eval<W, PV>(Bl, Bil, col, s, lc, nw, lane, mlist, rows, rins, joins, nodes, cnt, 0, 1);
-      else if (lc == 3)
+        cjoins += joins - j0;
+      } else if (lc == 3)
         tc = level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], nw, lane, vlist, joins, nodes, cnt, 0, 1);
       else {
         uint64_t j = 0;
@@ -803,13 +927,14 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   unsigned long long* tot = (unsigned long long*)wblk;
   uint64_t* rows = (uint64_t*)(wblk + 2 * K);
   uint64_t* rins = rows + 64;
-  int32_t* cur = (int32_t*)(wblk + 2 * K + (COMP ? 256 + 24 : 0));
+  int32_t* cur = (int32_t*)(wblk + 2 * K + (COMP ? 2 * (64 + 128 + 12) : 0));
   int32_t* chosen = cur + K;
   uint32_t* stk = (uint32_t*)(chosen + K);
   uint16_t* mlist = (uint16_t*)(stk + K * W);
   uint16_t* vlist = mlist + 64;
 
   uint64_t my_nodes = 0, my_isect = 0;  // per lane
+  uint64_t my_wide = 0, my_comp = 0;    // of which: wave-wide joins, joins on re-encoded 64-bit rows
 
   for (;;) {
     if (tid == 0) {
@@ -875,7 +1000,7 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       if (wid == 0) my_nodes += (lane == 0);
       const uint32_t c0w = lane < W ? C0[lane] : 0u;
       const uint64_t wave_total = eval_node<W, PV, COMP>(Bl, Bil, col, firstpos, s, L0, c0w, lane, stk, cur, chosen, tot,
-                                                   mlist, rows, rins, vlist, my_isect, my_nodes, cnt, wid, NW,
+                                                   mlist, rows, rins, vlist, my_isect, my_nodes, my_wide, my_comp, cnt, wid, NW,
                                                    a.cmax, a.clev, &sh[2]);
       {
         const uint64_t wt = kc_wave_sum_u64(wave_total);
@@ -903,7 +1028,10 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       // per-root work log (flushed per task)
       {
         const uint64_t wi = kc_wave_sum_u64(my_isect), wn = kc_wave_sum_u64(my_nodes);
+        const uint64_t ww = kc_wave_sum_u64(my_wide), wc = kc_wave_sum_u64(my_comp);
         if (lane == 0 && (wi || wn)) {
+          atomicAdd(&a.counters[3], (unsigned long long)ww);
+          atomicAdd(&a.counters[4], (unsigned long long)wc);
           if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
           if (a.root_work)
             atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)wi * (uint64_t)((s + 31) / 32));
@@ -914,6 +1042,8 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       }
       my_nodes = 0;
       my_isect = 0;
+      my_wide = 0;
+      my_comp = 0;
       __syncthreads();
     }
   }
@@ -1143,20 +1273,36 @@ __global__ void k_scatter_features(int32_t R, const int32_t* __restrict__ roots,
   out[4 * (int64_t)roots[i >> 2] + (i & 3)] = f[i];
 }
 
+// per-class counters (KC_NCTR each) into the call's totals: nodes, isect and
+// work to slots 0-2, the two join kinds to slots 4-5 (slot 3 is staging)
+#define KC_NCTR 5
 __global__ void k_add_counters(const unsigned long long* __restrict__ per_class, int ncls, unsigned long long* total) {
   int i = threadIdx.x;
-  if (i < 3) {
+  if (i < KC_NCTR) {
     unsigned long long t = 0;
-    for (int c = 0; c < ncls; ++c) t += per_class[3 * c + i];
-    total[i] += t;
+    for (int c = 0; c < ncls; ++c) t += per_class[KC_NCTR * c + i];
+    total[i < 3 ? i : i + 1] += t;
   }
 }
 
 // ============================================================== host side
 template <int W, int NW, bool PV>
+static size_t list_lds_bytes(const ListArgs& a) {
+  return a.cmax > 0 ? ListLayout<W, NW, PV, true>::bytes(a.k + 1) : ListLayout<W, NW, PV, false>::bytes(a.k + 1);
+}
+
+static size_t device_max_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 65536;
+  return (size_t)v;
+}
+
+template <int W, int NW, bool PV>
 static int launch_list(const ListArgs& a, hipStream_t st) {
   const bool comp = a.cmax > 0;
-  const size_t bytes = comp ? ListLayout<W, NW, PV, true>::bytes(a.k + 1) : ListLayout<W, NW, PV, false>::bytes(a.k + 1);
+  const size_t bytes = list_lds_bytes<W, NW, PV>(a);
   auto fn = comp ? k_bitcol_list<W, NW, PV, true> : k_bitcol_list<W, NW, PV, false>;
   KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   int per_cu = 0;
@@ -1172,9 +1318,12 @@ static int launch_list(const ListArgs& a, hipStream_t st) {
 
 template <int W, bool PV>
 static int launch_list_nw(const ListArgs& a, int nw, hipStream_t st) {
-  if (nw >= 8) return launch_list<W, 8, PV>(a, st);
-  if (nw >= 2) return launch_list<W, 4, PV>(a, st);
-  return launch_list<W, 1, PV>(a, st);
+  // fewer waves per root when the requested shape's LDS does not fit
+  const size_t lim = device_max_lds();
+  if (nw >= 8 && list_lds_bytes<W, 8, PV>(a) <= lim) return launch_list<W, 8, PV>(a, st);
+  if (nw >= 2 && list_lds_bytes<W, 4, PV>(a) <= lim) return launch_list<W, 4, PV>(a, st);
+  if (list_lds_bytes<W, 1, PV>(a) <= lim) return launch_list<W, 1, PV>(a, st);
+  return KC_EUNSUPPORTED;
 }
 
 static int launch_list_class(const ListArgs& a, int cls, int nw, bool pv, hipStream_t st) {
@@ -1435,8 +1584,8 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   int launches = 0;
   EventPair ev_cls[KC_NCLASS];
   unsigned long long* cls_ctr;
-  KC_TRY(scr.get(&cls_ctr, 3 * KC_NCLASS));
-  KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * 3 * KC_NCLASS, st));
+  KC_TRY(scr.get(&cls_ctr, KC_NCTR * KC_NCLASS));
+  KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * KC_NCTR * KC_NCLASS, st));
   // The classes' persistent kernels run concurrently on their own streams
   // (default priority) so that one class's tail overlaps the next class's work.
   struct Streams {
@@ -1481,7 +1630,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
     la.count = c.count;
     la.pv = c.pv;
-    la.counters = cls_ctr + 3 * cl;
+    la.counters = cls_ctr + KC_NCTR * cl;
     la.root_work = c.root_work;
     la.root_isect = c.root_isect;
     la.flags = c.flags;
@@ -1500,12 +1649,12 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     c.stats->list_ms += ev_list.ms();
     c.stats->list_launches += launches;
     c.stats->n_tasks += NT;
-    unsigned long long hc[3 * KC_NCLASS];
+    unsigned long long hc[KC_NCTR * KC_NCLASS];
     KC_HIP(hipMemcpyAsync(hc, cls_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     for (int cl = 0; cl < KC_NCLASS; ++cl) {
       if (ev_cls[cl].a) c.stats->class_ms[cl] = ev_cls[cl].ms();
-      c.stats->class_work[cl] = hc[3 * cl + 2];
+      c.stats->class_work[cl] = hc[KC_NCTR * cl + 2];
       c.stats->class_tasks[cl] = boff[(cl + 1) * 64] - boff[cl * 64];
     }
   }
