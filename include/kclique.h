@@ -99,8 +99,10 @@ typedef struct {
   int32_t chunk;          /* tasks taken per queue access: 0 = auto */
   int32_t split;          /* heavy-root splitting: 0 = auto, -1 = never, 1/2 = force that depth for heavy roots */
   float split_threshold;  /* 0 = auto: schedule key above which roots are split */
-  int32_t compress;       /* BitCol node re-encoding: 0 or -1 = off, else the largest candidate set
-                             (<= 64) re-encoded into 64-bit rows */
+  int32_t compress;       /* BitCol node re-encoding: the largest candidate set re-encoded into rows
+                             of one 64-bit word (sets <= 64) or, when counting without per-vertex
+                             output, two words (sets of 65..128).  0 = auto (128 when counting, 64
+                             per-vertex), -1 = off, else capped at those values */
   int32_t compress_level; /* BitCol: re-encode only nodes of level >= this (0 = auto) */
   /* optional per-vertex logs, device pointers of n entries (NULL = off):
    * the root's listing work (as kc_stats.work) and its features */

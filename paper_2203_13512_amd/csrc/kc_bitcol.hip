@@ -332,8 +332,8 @@ struct ListArgs {
 //   B[W][S+1] | Bin[W][S+1] (per-vertex) | color[S] | firstpos[KMAX+2] |
 //   C0[W] | shared scalars[16] | NW wave blocks | cnt[S] u64 (per-vertex)
 // A wave block (sized for K = k+1 levels at run time) holds tot[K] u64 |
-// (compressed variant) rows[64], rins or the level-2 queue[128], cm[12] u64 |
-// cur[K] | chosen[K] | stack[K][W] | member list[64] u16 | candidate list[S] u16.
+// cur[K] | chosen[K] | stack[K][W] | a region used by one evaluation at a
+// time: the candidate list of a level-3 node, or a re-encoded node.
 #define KC_KMAX 32
 
 template <int W, int NW, bool PV, bool COMP>
@@ -341,20 +341,26 @@ struct ListLayout {
   static constexpr int S = 32 * W;
   static constexpr int SP = S + 1;  // LDS row stride (bank-conflict free)
   static constexpr int a2(int x) { return (x + 1) & ~1; }
+  static constexpr int a4(int x) { return (x + 3) & ~3; }
   static constexpr int oB = 0;
   static constexpr int oBin = oB + W * SP;
   static constexpr int oCol = oBin + (PV ? W * SP : 0);
   static constexpr int oFirst = oCol + S;
   static constexpr int oC0 = oFirst + KC_KMAX + 2;
   static constexpr int oSh = a2(oC0 + W);
-  static constexpr int oWave = oSh + 16;
+  static constexpr int oWave = a4(oSh + 16);
+  // Two-word re-encoding (sets of 65..128 members) is used when counting.
+  static constexpr bool C2 = COMP && !PV && W >= 4 && W <= 16;
+  // Per-wave region used by one evaluation at a time: the candidate list of a
+  // lane-parallel level-3 node, or a re-encoded node (rows, queue or in-rows,
+  // color masks, member list).
+  static constexpr int U1 = 2 * (64 + 128 + 12) + 32;        // one-word rows
+  static constexpr int U2 = 4 * 128 + 4 * 128 + 4 * 12 + 64;  // two-word rows
+  static constexpr int UW = a4(S / 2 > (C2 ? U2 : (COMP ? U1 : 0)) ? S / 2 : (C2 ? U2 : (COMP ? U1 : 0)));
   // per wave, for recursion depth K = k + 1 (runtime):
-  //   tot[K] u64 | [rows[64] rins[128] cm[12] u64 (compressed variant; when
-  //   counting, rins holds the queue of level-2 nodes)] |
-  //   cur[K] | chosen[K] | stack[K][W] | mlist[64] u16 | vlist[S] u16
-  __host__ __device__ static constexpr int wave_words(int K) {
-    return a2(2 * K + (COMP ? 2 * (64 + 128 + 12) : 0) + 2 * K + K * W + 32 + S / 2);
-  }
+  //   tot[K] u64 | cur[K] | chosen[K] | stack[K][W] | (16-byte aligned) region[UW]
+  __host__ __device__ static constexpr int oU(int K) { return a4(2 * K + 2 * K + K * W); }
+  __host__ __device__ static constexpr int wave_words(int K) { return oU(K) + UW; }
   __host__ __device__ static constexpr int oCnt(int K) { return oWave + NW * wave_words(K); }
   __host__ __device__ static constexpr int words(int K) { return oCnt(K) + (PV ? 2 * S : 0); }
   static size_t bytes(int K) { return 4 * (size_t)words(K); }
@@ -515,6 +521,7 @@ __device__ __forceinline__ uint64_t level3_eval(const uint32_t* __restrict__ Bl,
 // (cdfs<L>), so the walk's sets stay in registers.
 #define KC_CMAX 10  // deepest level evaluated on compressed rows
 #define KC_QMAX 8   // deepest level evaluated through the level-2 queue (count mode)
+#define KC_Q2MAX 5  // the same for two-word rows (children of wide nodes only)
 
 struct CNode {
   const uint64_t* rows;   // R_j (LDS)
@@ -659,6 +666,209 @@ __device__ __forceinline__ void wdfs(CQueue& Q, const uint64_t* __restrict__ cm,
   }
 }
 
+// ---- count-only evaluation of compressed nodes of 65 to 128 members --------
+// Same scheme with two-word sets: lane i holds the row of member i (one word:
+// R_i only has members below i) and of member 64+i (two words).  Rows live in
+// LDS as four 32-bit words each, the level-2 queue as pairs of 64-bit words.
+
+// Leaves of a level-2 node X = (xl, xh): a member in 32-bit word q of X has
+// nonzero row words 0..q only.
+__device__ __forceinline__ uint32_t cleaf2(const uint32_t* __restrict__ r, uint64_t xl, uint64_t xh, uint64_t c2l,
+                                           uint64_t c2h) {
+  const uint32_t x0 = (uint32_t)xl, x1 = (uint32_t)(xl >> 32), x2 = (uint32_t)xh, x3 = (uint32_t)(xh >> 32);
+  const uint64_t cl = xl & c2l, ch = xh & c2h;
+  uint32_t w0 = (uint32_t)cl, w1 = (uint32_t)(cl >> 32), w2 = (uint32_t)ch, w3 = (uint32_t)(ch >> 32);
+  uint32_t acc = 0;
+  while (w0) {
+    const int y = __ffs((int)w0) - 1;
+    w0 &= w0 - 1;
+    acc += (uint32_t)__popc(r[4 * y] & x0);
+  }
+  while (w1) {
+    const int y = __ffs((int)w1) + 31;
+    w1 &= w1 - 1;
+    const uint2 v = *(const uint2*)(r + 4 * y);
+    acc += (uint32_t)__popc(v.x & x0) + (uint32_t)__popc(v.y & x1);
+  }
+  while (w2) {
+    const int y = __ffs((int)w2) + 63;
+    w2 &= w2 - 1;
+    const uint4 v = *(const uint4*)(r + 4 * y);
+    acc += (uint32_t)__popc(v.x & x0) + (uint32_t)__popc(v.y & x1) + (uint32_t)__popc(v.z & x2);
+  }
+  while (w3) {
+    const int y = __ffs((int)w3) + 95;
+    w3 &= w3 - 1;
+    const uint4 v = *(const uint4*)(r + 4 * y);
+    acc += (uint32_t)__popc(v.x & x0) + (uint32_t)__popc(v.y & x1) + (uint32_t)__popc(v.z & x2) +
+           (uint32_t)__popc(v.w & x3);
+  }
+  return acc;
+}
+
+struct CQueue2 {
+  const uint32_t* rows;  // 128 rows x 4 words (LDS)
+  uint64_t* q;           // 128 pending level-2 nodes x 2 words (LDS, per wave)
+  int n;
+  uint64_t c2l, c2h, c3l, c3h;
+  uint64_t acc;
+};
+
+__device__ __forceinline__ void cq2_eval(CQueue2& Q, int lane, int cnt_lanes, uint64_t& joins) {
+  kc_wave_lds_sync();
+  if (lane < cnt_lanes) {
+    const int e = Q.n - cnt_lanes + lane;
+    const uint64_t yl = Q.q[2 * e], yh = Q.q[2 * e + 1];
+    joins += (uint64_t)(__popcll(yl & Q.c2l) + __popcll(yh & Q.c2h));
+    Q.acc += cleaf2(Q.rows, yl, yh, Q.c2l, Q.c2h);
+  }
+  Q.n -= cnt_lanes;
+  kc_wave_lds_sync();
+}
+
+// Appends the qualifying children of the candidates in `cand` (one per lane).
+__device__ __forceinline__ void cq2_push(CQueue2& Q, bool cand, uint64_t yl, uint64_t yh, int lane, uint64_t& joins,
+                                         uint64_t& nodes) {
+  joins += cand ? 1u : 0u;
+  const bool push = cand && (__popcll(yl) + __popcll(yh)) >= 2;
+  nodes += push ? 1u : 0u;
+  const uint64_t pm = kc_ballot(push);
+  if (push) {
+    const int e = Q.n + kc_mbcnt(pm);
+    Q.q[2 * e] = yl;
+    Q.q[2 * e + 1] = yh;
+  }
+  Q.n += __popcll(pm);
+  if (Q.n >= 64) cq2_eval(Q, lane, 64, joins);
+}
+
+template <int L>
+__device__ __forceinline__ void wdfs2(CQueue2& Q, const uint64_t* __restrict__ cm, uint64_t R0, uint64_t R1l,
+                                      uint64_t R1h, uint64_t Xl, uint64_t Xh, uint64_t topl, uint64_t toph, int lane,
+                                      uint64_t& joins, uint64_t& nodes) {
+  if constexpr (L == 3) {
+    cq2_push(Q, ((Xl & Q.c3l & topl) >> lane) & 1ull, R0 & Xl, 0ull, lane, joins, nodes);
+    cq2_push(Q, ((Xh & Q.c3h & toph) >> lane) & 1ull, R1l & Xl, R1h & Xh, lane, joins, nodes);
+  } else {
+    uint64_t cl = Xl & readfirstlane64(cm[2 * L]) & topl;
+    uint64_t ch = Xh & readfirstlane64(cm[2 * L + 1]) & toph;
+    while (cl) {
+      const int y = __ffsll((long long)cl) - 1;
+      cl &= cl - 1;
+      const uint64_t Yl = readlane64(R0, y) & Xl;
+      joins += (lane == 0);
+      if (__popcll(Yl) >= L - 1) {
+        nodes += (lane == 0);
+        wdfs2<L - 1>(Q, cm, R0, R1l, R1h, Yl, 0ull, ~0ull, ~0ull, lane, joins, nodes);
+      }
+    }
+    while (ch) {
+      const int y = __ffsll((long long)ch) - 1;
+      ch &= ch - 1;
+      const uint64_t Yl = readlane64(R1l, y) & Xl, Yh = readlane64(R1h, y) & Xh;
+      joins += (lane == 0);
+      if (__popcll(Yl) + __popcll(Yh) >= L - 1) {
+        nodes += (lane == 0);
+        wdfs2<L - 1>(Q, cm, R0, R1l, R1h, Yl, Yh, ~0ull, ~0ull, lane, joins, nodes);
+      }
+    }
+  }
+}
+
+// Node of level l (4 <= l <= KC_QMAX) whose set C (lane-split `cw`) has 65 to
+// 128 members, counted; candidates dealt to `nparts` waves.  `ureg` is the
+// wave's evaluation region (16-byte aligned).  It has a single call site (a
+// child of a wide node) and unrolls levels 4 and 5 only: every further
+// inlined copy of the unrolled levels adds to the register footprint of the
+// whole listing kernel.
+template <int W>
+__device__ __forceinline__ uint64_t compressed_eval2(const uint32_t* __restrict__ Bl,
+                                                     const uint32_t* __restrict__ col, int s, int l, uint32_t cw,
+                                                     int lane, uint32_t* __restrict__ ureg, uint64_t& joins,
+                                                     uint64_t& nodes, int part, int nparts) {
+  constexpr int SP = 32 * W + 1;
+  uint32_t* rows = ureg;                         // [128][4]
+  uint64_t* q = (uint64_t*)(ureg + 512);         // [128][2]
+  uint64_t* cm = (uint64_t*)(ureg + 1024);       // [KC_CMAX+1][2]
+  uint16_t* mlist = (uint16_t*)(ureg + 1072);    // [128]
+  const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
+  if (hiw < 0) return 0;
+  const int end = (hiw + 1) * 32 < s ? (hiw + 1) * 32 : s;
+  int m = 0;
+  for (int p0 = 0; p0 < end; p0 += 64) {
+    const int p = p0 + lane;
+    const uint32_t word = (uint32_t)__shfl((int)cw, (p >> 5) & 63, 64);
+    const bool mem = p < end && ((word >> (p & 31)) & 1u);
+    const uint64_t mk = kc_ballot(mem);
+    if (mem) mlist[m + kc_mbcnt(mk)] = (uint16_t)p;
+    m += __popcll(mk);
+  }
+  kc_wave_lds_sync();
+  const bool valid0 = lane < m, valid1 = lane + 64 < m;
+  const int v0 = valid0 ? mlist[lane] : 0, v1 = valid1 ? mlist[lane + 64] : 0;
+  // rows: member i = lane gets R0 (members below 64), member 64+lane gets (R1l, R1h)
+  uint64_t R0 = 0, R1l = 0, R1h = 0;
+  {
+    int curw = -1;
+    uint32_t b0 = 0, b1 = 0;
+    const int m0 = m < 64 ? m : 64;
+    for (int jj = 0; jj < m0; ++jj) {
+      const int p = __builtin_amdgcn_readlane(v0, jj);
+      const int wd = p >> 5;
+      if (wd != curw) {
+        curw = wd;
+        b0 = valid0 ? Bl[wd * SP + v0] : 0u;
+        b1 = valid1 ? Bl[wd * SP + v1] : 0u;
+      }
+      R0 |= (uint64_t)((b0 >> (p & 31)) & 1u) << jj;
+      R1l |= (uint64_t)((b1 >> (p & 31)) & 1u) << jj;
+    }
+    for (int jj = 64; jj < m; ++jj) {
+      const int p = __builtin_amdgcn_readlane(v1, jj - 64);
+      const int wd = p >> 5;
+      if (wd != curw) {
+        curw = wd;
+        b1 = valid1 ? Bl[wd * SP + v1] : 0u;
+      }
+      R1h |= (uint64_t)((b1 >> (p & 31)) & 1u) << (jj - 64);
+    }
+  }
+  *(uint2*)(rows + 4 * lane) = make_uint2((uint32_t)R0, (uint32_t)(R0 >> 32));
+  *(uint2*)(rows + 4 * lane + 2) = make_uint2(0u, 0u);
+  *(uint4*)(rows + 4 * (lane + 64)) =
+      make_uint4((uint32_t)R1l, (uint32_t)(R1l >> 32), (uint32_t)R1h, (uint32_t)(R1h >> 32));
+  const int c0 = valid0 ? (int)col[v0] : 0, c1 = valid1 ? (int)col[v1] : 0;
+#pragma unroll
+  for (int c = 0; c <= KC_CMAX; ++c) {
+    const uint64_t bl = kc_ballot(valid0 && c0 >= c), bh = kc_ballot(valid1 && c1 >= c);
+    if (lane == 0) {
+      cm[2 * c] = bl;
+      cm[2 * c + 1] = bh;
+    }
+  }
+  CQueue2 Q;
+  Q.rows = rows;
+  Q.q = q;
+  Q.n = 0;
+  Q.c2l = kc_ballot(valid0 && c0 >= 2);
+  Q.c2h = kc_ballot(valid1 && c1 >= 2);
+  Q.c3l = kc_ballot(valid0 && c0 >= 3);
+  Q.c3h = kc_ballot(valid1 && c1 >= 3);
+  Q.acc = 0;
+  const uint64_t Xl = kc_ballot(valid0), Xh = kc_ballot(valid1);
+  uint64_t deal = 0;
+  for (int j = part; j < 64; j += nparts) deal |= 1ull << j;
+  // member 64+i is dealt like member i when nparts divides 64 (1, 4 or 8)
+  kc_wave_lds_sync();
+#define KC_WD2(LL) \
+  case LL: wdfs2<LL>(Q, cm, R0, R1l, R1h, Xl, Xh, deal, deal, lane, joins, nodes); break;
+  switch (l) { KC_WD2(4) KC_WD2(5) }
+#undef KC_WD2
+  if (Q.n > 0) cq2_eval(Q, lane, Q.n, joins);
+  kc_wave_lds_sync();
+  return Q.acc;
+}
+
 // Subtree below candidate j's BitJoin at a node of level l: X2 = R_j.
 template <bool PV>
 __device__ __forceinline__ uint64_t cdfs_dispatch(int l, const CNode& nd, uint64_t X2, uint64_t& joins,
@@ -792,10 +1002,11 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
                               uint16_t* __restrict__ mlist, uint64_t* __restrict__ rows, uint64_t* __restrict__ rins,
                               uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes, uint64_t& wjoins,
                               uint64_t& cjoins, unsigned long long* cnt, int part, int nparts, int cmax, int clev,
-                              int32_t* __restrict__ shared_next) {
+                              int32_t* __restrict__ shared_next, uint32_t* __restrict__ ureg) {
   constexpr int SP = 32 * W + 1;
+  constexpr bool C2 = COMP && !PV && W >= 4 && W <= 16;
   const uint32_t m = split_popc(cw);
-  if (COMP && (int)m <= cmax && L <= KC_CMAX && L >= clev) {
+  if (COMP && (int)m <= cmax && (int)m <= 64 && L <= KC_CMAX && L >= clev) {
     const uint64_t j0 = joins;
     const uint64_t t = compressed_eval<W, PV>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt,
                                               part, nparts);
@@ -866,12 +1077,17 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
     if ((int)npc < l - 1) continue;
     nodes += (lane == 0);
     const int lc = l - 1;
-    const bool comp = COMP && (int)npc <= cmax && lc <= KC_CMAX && lc >= clev;
-    if (comp || lc <= 3) {
+    const bool comp = COMP && (int)npc <= cmax && (int)npc <= 64 && lc <= KC_CMAX && lc >= clev;
+    const bool comp2 = C2 && !comp && (int)npc <= cmax && lc <= KC_Q2MAX && lc >= clev && lc >= 4;
+    if (comp || comp2 || lc <= 3) {
       uint64_t tc;
       if (COMP && comp) {
         const uint64_t j0 = joins;
         tc = compressed_eval<W, PV>(Bl, Bil, col, s, lc, nw, lane, mlist, rows, rins, joins, nodes, cnt, 0, 1);
+        cjoins += joins - j0;
+      } else if (C2 && comp2) {
+        const uint64_t j0 = joins;
+        tc = compressed_eval2<W>(Bl, col, s, lc, nw, lane, ureg, joins, nodes, 0, 1);
         cjoins += joins - j0;
       } else if (lc == 3)
         tc = level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], nw, lane, vlist, joins, nodes, cnt, 0, 1);
@@ -905,7 +1121,8 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
 }
 
 template <int W, int NW, bool PV, bool COMP>
-__global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
+// At least 4 waves per SIMD: the register budget stays at 128 VGPRs.
+__global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
   using LY = ListLayout<W, NW, PV, COMP>;
   const int K = a.k + 1;
   constexpr int S = LY::S;
@@ -925,13 +1142,14 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
   const int lane = tid & 63;
   uint32_t* wblk = lds + LY::oWave + wid * LY::wave_words(K);
   unsigned long long* tot = (unsigned long long*)wblk;
-  uint64_t* rows = (uint64_t*)(wblk + 2 * K);
-  uint64_t* rins = rows + 64;
-  int32_t* cur = (int32_t*)(wblk + 2 * K + (COMP ? 2 * (64 + 128 + 12) : 0));
+  int32_t* cur = (int32_t*)(wblk + 2 * K);
   int32_t* chosen = cur + K;
   uint32_t* stk = (uint32_t*)(chosen + K);
-  uint16_t* mlist = (uint16_t*)(stk + K * W);
-  uint16_t* vlist = mlist + 64;
+  uint32_t* ureg = wblk + LY::oU(K);
+  uint16_t* vlist = (uint16_t*)ureg;
+  uint64_t* rows = (uint64_t*)ureg;  // rows[64] | rins or queue[128] | cm[12] | mlist[64] u16
+  uint64_t* rins = rows + 64;
+  uint16_t* mlist = (uint16_t*)(rows + 204);
 
   uint64_t my_nodes = 0, my_isect = 0;  // per lane
   uint64_t my_wide = 0, my_comp = 0;    // of which: wave-wide joins, joins on re-encoded 64-bit rows
@@ -1001,7 +1219,7 @@ __global__ __launch_bounds__(64 * NW) void k_bitcol_list(ListArgs a) {
       const uint32_t c0w = lane < W ? C0[lane] : 0u;
       const uint64_t wave_total = eval_node<W, PV, COMP>(Bl, Bil, col, firstpos, s, L0, c0w, lane, stk, cur, chosen, tot,
                                                    mlist, rows, rins, vlist, my_isect, my_nodes, my_wide, my_comp, cnt, wid, NW,
-                                                   a.cmax, a.clev, &sh[2]);
+                                                   a.cmax, a.clev, &sh[2], ureg);
       {
         const uint64_t wt = kc_wave_sum_u64(wave_total);
         if (lane == 0 && wt) atomicAdd(&shtot[0], (unsigned long long)wt);
@@ -1626,7 +1844,11 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     la.k = c.k;
     la.vk = c.vk;
     la.root_count = c.root_count;
-    la.cmax = opt && opt->compress > 0 ? (opt->compress > 64 ? 64 : opt->compress) : 0;
+    {
+      const int cap = pv ? 64 : 128;  // two-word re-encoding only when counting
+      const int want = opt ? opt->compress : 0;  // 0 = auto: the cap; < 0 = off
+      la.cmax = want == 0 ? cap : (want < 0 ? 0 : (want > cap ? cap : want));
+    }
     la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
     la.count = c.count;
     la.pv = c.pv;

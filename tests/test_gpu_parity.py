@@ -218,7 +218,9 @@ def test_schedule_does_not_change_results(order):
         want, wpv = oracle.count(*g, k, per_vertex=True)
         base = None
         for kw in [dict(), dict(split=1, split_threshold=1.0), dict(split=2, split_threshold=1.0),
-                   dict(waves_per_root=1), dict(waves_per_root=2, chunk=3), dict(split=-1, waves_per_root=4)]:
+                   dict(waves_per_root=1), dict(waves_per_root=2, chunk=3), dict(split=-1, waves_per_root=4),
+                   dict(compress=-1), dict(compress=64, compress_level=2), dict(compress=20, compress_level=3),
+                   dict(compress=128, compress_level=5, waves_per_root=8)]:
             say("schedule invariance", k, kw)
             c, st, lg = _logs(g, k, order, **kw)
             assert c == want, kw
@@ -230,6 +232,49 @@ def test_schedule_does_not_change_results(order):
                 assert np.array_equal(lg["isect"], base[1]["isect"]), kw
                 assert np.array_equal(lg["work"], base[1]["work"]), kw
                 assert st["nodes"] == base[0]["nodes"], kw
+
+
+# Re-encoding settings (the largest set re-encoded, the lowest level, waves per
+# root): off, one-word rows at every level, one-word rows from level 4 with
+# the level-2 queue, and two-word rows (sets of 65..128) when counting.
+REENCODE = [dict(compress=-1), dict(compress=64, compress_level=2), dict(compress=64, compress_level=4),
+            dict(compress=128, compress_level=4), dict(compress=128, compress_level=6, waves_per_root=1),
+            dict(compress=100, compress_level=4, waves_per_root=4, split=2, split_threshold=1.0)]
+
+
+@pytest.mark.parametrize("parts,ks", [((2,) * 64, (5, 6, 7)), ((3,) * 40, (5, 7)),
+                                      ((1,) * 90 + (2,) * 10, (5, 6)), ((7, 5, 4, 3, 3, 2, 2) + (1,) * 60, (6, 8))])
+def test_reencoded_nodes_closed_forms(parts, ks):
+    """Dense complete multipartite graphs of 110..128 vertices: their nodes
+    of level >= 4 hold up to about 125 candidates, so every re-encoding path
+    runs.  Counts equal e_k of the part sizes; per-vertex values equal
+    e_{k-1} of the other parts; joins and nodes do not depend on the setting."""
+    (rp, ci), owner = G.multipartite(parts)
+    g = (rp, ci)
+    for k in ks:
+        want = G.elementary_symmetric(parts, k)
+        base = None
+        comp = []
+        for kw in REENCODE:
+            say("re-encoding", len(owner), k, kw)
+            c, st, lg = _logs(g, k, "color", **kw)
+            assert c == want, kw
+            comp.append(st["isect_compressed"])
+            if base is None:
+                base = (st, lg)
+            else:
+                assert np.array_equal(lg["isect"], base[1]["isect"]), kw
+                assert np.array_equal(lg["work"], base[1]["work"]), kw
+                assert st["nodes"] == base[0]["nodes"] and st["isect"] == base[0]["isect"], kw
+        assert comp[0] == 0 and comp[3] >= comp[2] > 0, comp
+        if k >= 6:  # children of the root's level are at level >= 4: two-word rows take them
+            assert comp[3] > comp[2], comp
+        say("re-encoding per-vertex", len(owner), k)
+        c, pv = gpv(g, k, "color")
+        assert c == want
+        for i in {0, len(owner) // 2, len(owner) - 1}:
+            rest = [a for j, a in enumerate(parts) if j != owner[i]]
+            assert int(pv[i]) == G.elementary_symmetric(rest, k - 1)
 
 
 # ------------------------------------------------------- scaled workloads
