@@ -104,6 +104,9 @@ typedef struct {
                              output, two words (sets of 65..128).  0 = auto (128 when counting, 64
                              per-vertex), -1 = off, else capped at those values */
   int32_t compress_level; /* BitCol: re-encode only nodes of level >= this (0 = auto) */
+  int32_t class_streams;  /* BitCol: listing kernels of the word classes 1 = one after another on `stream`,
+                             2 = concurrently on streams of their own, 0 = auto (1 for the learned
+                             schedule, 2 for the degree schedule) */
   /* optional per-vertex logs, device pointers of n entries (NULL = off):
    * the root's listing work (as kc_stats.work) and its features */
   uint64_t* root_work;

@@ -61,6 +61,7 @@ class Options(ctypes.Structure):
         ("schedule", ctypes.c_int32), ("mlp_params", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p),
         ("waves_per_root", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
         ("split_threshold", ctypes.c_float), ("compress", ctypes.c_int32), ("compress_level", ctypes.c_int32),
+        ("class_streams", ctypes.c_int32),
         ("root_work", ctypes.c_void_p), ("root_isect", ctypes.c_void_p),
         ("root_features", ctypes.c_void_p), ("root_count", ctypes.c_void_p), ("vertex_k", ctypes.c_void_p),
         ("stats", ctypes.POINTER(Stats)),
@@ -122,8 +123,8 @@ def _check(st: int, what: str):
 
 def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False, schedule: str = "degree",
           mlp=None, trusted: bool = False, waves_per_root: int = 0, chunk: int = 0, split: int = 0,
-          split_threshold: float = 0.0, compress: int = 0, compress_level: int = 0, root_logs: bool = False,
-          stats: bool = False):
+          split_threshold: float = 0.0, compress: int = 0, compress_level: int = 0, class_streams: int = 0,
+          root_logs: bool = False, stats: bool = False):
     """Number of k-cliques (and per-vertex participation).
 
     Returns ``count`` or, with ``per_vertex``, ``(count, pv)`` where pv[v]
@@ -146,6 +147,7 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
     opt.split_threshold = split_threshold
     opt.compress = compress
     opt.compress_level = compress_level
+    opt.class_streams = class_streams
     out = ctypes.c_uint64(0)
     keep = []
     on_gpu = _is_torch(row_ptr) and row_ptr.is_cuda

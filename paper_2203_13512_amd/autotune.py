@@ -7,13 +7,14 @@ width of the bitmaps the deepest levels run on), and how many queue items a
 workgroup takes per access (chunking).  None of them changes a result.
 
 The objective is the device time of the listing kernels (HIP events, from the
-call's statistics) on a proxy of the problem: the same graph at k-1 when
-k >= 7 (about ten times less work, same sets and the same shape of the search
-tree near its leaves), else the problem itself.  Decisions are cached in
-autotune.json next to this module, keyed by a signature of the graph and k.
+call's statistics) on the problem itself, or on a cheaper proxy when asked
+(the same graph at k-1: about ten times less work, but its best launch shape
+can differ).  Decisions are cached in autotune.json next to this module,
+keyed by a signature of the graph and k.
 
-Run ``python -m paper_2203_13512_amd.autotune [workload ...]`` on a GPU to
-tune the synthetic workloads and write the cache.
+Run ``python -m paper_2203_13512_amd.autotune [workload:k ...]`` on a GPU to
+tune the synthetic workloads (with the learned schedule when a model for k
+exists) and write the cache.
 """
 from __future__ import annotations
 
@@ -30,12 +31,14 @@ import paper_2203_13512_amd as kc
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json")
 
 SPACE = [
-    {"waves_per_root": 4, "compress": -1},
-    {"waves_per_root": 8, "compress": -1},
-    {"waves_per_root": 4, "compress": 64, "compress_level": 4},
-    {"waves_per_root": 8, "compress": 64, "compress_level": 4},
-    {"waves_per_root": 8, "compress": 64, "compress_level": 5},
-    {"waves_per_root": 8, "compress": 64, "compress_level": 4, "chunk": 1},
+    {},  # library defaults: waves per root by word class, re-encoding up to 128 members from level 4
+    {"waves_per_root": 4},
+    {"waves_per_root": 8},
+    {"compress": 64},
+    {"compress_level": 3},
+    {"compress_level": 5},
+    {"waves_per_root": 8, "compress": 64},
+    {"waves_per_root": 8, "class_streams": 2},
 ]
 
 
@@ -61,10 +64,10 @@ def lookup(row_ptr, col_idx, k: int, order: str = "color", path: str = CACHE) ->
     return dict(e["best"]) if e else {}
 
 
-def tune(row_ptr, col_idx, k: int, order: str = "color", space=SPACE, log=print, **count_kw):
-    """Times every candidate on the proxy problem; returns (best, table)."""
+def tune(row_ptr, col_idx, k: int, order: str = "color", space=SPACE, log=print, proxy: bool = False, **count_kw):
+    """Times every candidate (on the k-1 proxy if `proxy`); returns (best, table)."""
     import torch
-    kp = k - 1 if k >= 7 else k
+    kp = k - 1 if (proxy and k >= 4) else k
     table = []
     for cand in space:
         kw = dict(count_kw)
@@ -85,18 +88,22 @@ def main(argv=None):
 
     import graphgen
     argv = argv if argv is not None else sys.argv[1:]
-    jobs = [tuple(int(x) for x in a.split(":")) for a in argv] or [(5, 8), (2, 7), (3, 8)]
+    from paper_2203_13512_amd import scheduler
+    jobs = [tuple(int(x) for x in a.split(":")) for a in argv] or [(5, 8), (5, 7), (2, 7)]
     cache = load_cache()
     dev = torch.device("cuda:0")
     for cfg, k in jobs:
+        mlp = scheduler.load_model(dev, k)
+        kw = dict(schedule="learned", mlp=mlp) if mlp is not None else {}
         w = graphgen.workload(cfg)
         rp_h, ci_h = w.graphs[0]
         rp = torch.from_numpy(rp_h).to(dev)
         ci = torch.from_numpy(ci_h).to(dev)
         t = time.time()
         print(f"{w.name} k={k}", flush=True)
-        best, info = tune(rp, ci, k, "color")
-        cache[signature(rp_h, ci_h, k, "color")] = dict(workload=w.name, k=k, order="color", best=best, **info)
+        best, info = tune(rp, ci, k, "color", **kw)
+        cache[signature(rp_h, ci_h, k, "color")] = dict(workload=w.name, k=k, order="color",
+                                                        schedule=kw.get("schedule", "degree"), best=best, **info)
         print(f"  best {best} ({time.time() - t:.1f}s)", flush=True)
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1)

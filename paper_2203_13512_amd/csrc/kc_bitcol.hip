@@ -1804,8 +1804,13 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   unsigned long long* cls_ctr;
   KC_TRY(scr.get(&cls_ctr, KC_NCTR * KC_NCLASS));
   KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * KC_NCTR * KC_NCLASS, st));
-  // The classes' persistent kernels run concurrently on their own streams
-  // (default priority) so that one class's tail overlaps the next class's work.
+  // One persistent kernel per word class, heaviest class first.  They either
+  // follow each other on the call's stream, or run concurrently on streams of
+  // their own (default priority) so that one class's tail overlaps the next
+  // class's work.  Auto: the learned schedule splits every class's heavy
+  // roots by its own predicted work and leaves no long tails, so its classes
+  // run in sequence; the degree schedule's tails are overlapped.
+  const int cmode = opt && opt->class_streams > 0 ? opt->class_streams : (learned ? 1 : 2);
   struct Streams {
     hipStream_t s[KC_NCLASS] = {};
     hipEvent_t done[KC_NCLASS] = {};
@@ -1823,11 +1828,15 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   for (int cl = KC_NCLASS - 1; cl >= 0; --cl) {
     int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
     if (hi <= lo) continue;
-    KC_HIP(hipStreamCreateWithFlags(&cs.s[cl], hipStreamNonBlocking));
-    KC_HIP(hipEventCreateWithFlags(&cs.done[cl], hipEventDisableTiming));
-    KC_HIP(hipStreamWaitEvent(cs.s[cl], ready, 0));
+    hipStream_t ls = st;
+    if (cmode == 2) {
+      KC_HIP(hipStreamCreateWithFlags(&cs.s[cl], hipStreamNonBlocking));
+      KC_HIP(hipEventCreateWithFlags(&cs.done[cl], hipEventDisableTiming));
+      KC_HIP(hipStreamWaitEvent(cs.s[cl], ready, 0));
+      ls = cs.s[cl];
+    }
     KC_TRY(ev_cls[cl].init());
-    KC_HIP(hipEventRecord(ev_cls[cl].a, cs.s[cl]));
+    KC_HIP(hipEventRecord(ev_cls[cl].a, ls));
     ListArgs la;
     la.roots = c.roots;
     la.ri = ri;
@@ -1856,10 +1865,12 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     la.root_work = c.root_work;
     la.root_isect = c.root_isect;
     la.flags = c.flags;
-    KC_TRY(launch_list_class(la, cl, nw, pv, cs.s[cl]));
-    KC_HIP(hipEventRecord(ev_cls[cl].b, cs.s[cl]));
-    KC_HIP(hipEventRecord(cs.done[cl], cs.s[cl]));
-    KC_HIP(hipStreamWaitEvent(st, cs.done[cl], 0));
+    KC_TRY(launch_list_class(la, cl, nw, pv, ls));
+    KC_HIP(hipEventRecord(ev_cls[cl].b, ls));
+    if (cmode == 2) {
+      KC_HIP(hipEventRecord(cs.done[cl], ls));
+      KC_HIP(hipStreamWaitEvent(st, cs.done[cl], 0));
+    }
     launches++;
   }
   k_add_counters<<<1, 64, 0, st>>>(cls_ctr, KC_NCLASS, c.counters);

@@ -220,7 +220,8 @@ def test_schedule_does_not_change_results(order):
         for kw in [dict(), dict(split=1, split_threshold=1.0), dict(split=2, split_threshold=1.0),
                    dict(waves_per_root=1), dict(waves_per_root=2, chunk=3), dict(split=-1, waves_per_root=4),
                    dict(compress=-1), dict(compress=64, compress_level=2), dict(compress=20, compress_level=3),
-                   dict(compress=128, compress_level=5, waves_per_root=8)]:
+                   dict(compress=128, compress_level=5, waves_per_root=8), dict(class_streams=1),
+                   dict(class_streams=2, waves_per_root=8)]:
             say("schedule invariance", k, kw)
             c, st, lg = _logs(g, k, order, **kw)
             assert c == want, kw
