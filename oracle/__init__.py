@@ -66,6 +66,7 @@ def _load():
         "orc_greedy_color": [i32, vp, vp, vp, vp],
         "orc_bitcol_encode": [i32, vp, vp, i32, vp, vp],
         "orc_bitcol_dag": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp],
+        "orc_bitcol_roots": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
         "orc_method_count": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     }
@@ -259,6 +260,19 @@ def bitcol_dag(drp, dci, k: int, L: int = 32):
     d["colors"] = colors[:n]
     d["edges"] = edges[:n]
     return int(c[0]), d
+
+
+def bitcol_roots(drp, dci, k: int, roots, L: int = 32):
+    """BitCol from the listed roots of the DAG only; dict of per-root arrays
+    (count, nodes, isect, words) in the order of `roots`."""
+    drp, dci = _csr(drp, dci)
+    n = len(drp) - 1
+    roots = np.ascontiguousarray(roots, dtype=np.int32)
+    r = max(len(roots), 1)
+    u = [np.zeros(r, dtype=np.uint64) for _ in range(4)]
+    _check(_load().orc_bitcol_roots(n, _p(drp), _p(dci), k, L, len(roots), _p(roots), *[_p(a) for a in u]),
+           "bitcol_roots")
+    return dict(zip(["count", "nodes", "isect", "words"], [a[:len(roots)] for a in u]))
 
 
 def method_count(rp, ci, k: int, method: str, L: int = 32):

@@ -664,6 +664,84 @@ int orc_bitcol_encode(int32_t s, const uint8_t* adj, const int32_t* ids, int32_t
   return ORC_OK;
 }
 
+/* Work space of the per-root BitCol evaluation. */
+typedef struct {
+  int32_t md, nwmax;
+  uint8_t* adj;
+  int32_t* ids;
+  int32_t* color;
+  uint32_t* B;
+  uint32_t* stack;
+  int32_t* pos;
+} bitcol_ws_t;
+
+static void bitcol_ws_free(bitcol_ws_t* w) {
+  free(w->adj); free(w->ids); free(w->color); free(w->B); free(w->stack); free(w->pos);
+}
+
+static int bitcol_ws_init(bitcol_ws_t* w, int32_t n, const int32_t* drp, int32_t k, int32_t L) {
+  memset(w, 0, sizeof(*w));
+  for (int32_t u = 0; u < n; ++u)
+    if (drp[u + 1] - drp[u] > w->md) w->md = drp[u + 1] - drp[u];
+  w->nwmax = (w->md + L - 1) / L + 1;
+  w->adj = (uint8_t*)malloc((size_t)w->md * (size_t)w->md + 1);
+  w->ids = (int32_t*)malloc(sizeof(int32_t) * ((size_t)w->md + 1));
+  w->color = (int32_t*)malloc(sizeof(int32_t) * ((size_t)w->md + 1));
+  w->B = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)w->md + 1) * (size_t)w->nwmax);
+  w->stack = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)w->nwmax * ((size_t)k + 2));
+  w->pos = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  if (!w->adj || !w->ids || !w->color || !w->B || !w->stack || !w->pos) {
+    bitcol_ws_free(w);
+    return ORC_ENOMEM;
+  }
+  for (int32_t v = 0; v < n; ++v) w->pos[v] = -1;
+  return ORC_OK;
+}
+
+/* BitCol (Alg. 6) from one root u of the DAG: builds G_u from N+(u), colors
+ * and encodes it, and runs the listing from the top call.  Adds to S's
+ * counters; reports the number of colors and |E_u|. */
+static int bitcol_root(bitcol_t* S, bitcol_ws_t* w, const int32_t* drp, const int32_t* dcol, int32_t k,
+                       int32_t L, int32_t u, int32_t* ncolors_out, int64_t* edges_out) {
+  int32_t s = drp[u + 1] - drp[u];
+  *ncolors_out = 0;
+  *edges_out = 0;
+  if (s < k - 1) return ORC_OK;
+  /* G_u: induced by N+(u), local index = position in N+(u) */
+  for (int32_t i = 0; i < s; ++i) { w->ids[i] = dcol[drp[u] + i]; w->pos[w->ids[i]] = i; }
+  memset(w->adj, 0, (size_t)s * (size_t)s);
+  int64_t ecount = 0;
+  for (int32_t i = 0; i < s; ++i) {
+    int32_t v = w->ids[i];
+    for (int32_t j = drp[v]; j < drp[v + 1]; ++j) {
+      int32_t x = dcol[j];
+      if (w->pos[x] >= 0) {
+        w->adj[(size_t)i * s + w->pos[x]] = 1;
+        w->adj[(size_t)w->pos[x] * s + i] = 1;
+        ecount++;
+      }
+    }
+  }
+  for (int32_t i = 0; i < s; ++i) w->pos[w->ids[i]] = -1;
+  int st = orc_bitcol_encode(s, w->adj, w->ids, L, w->color, w->B);
+  if (st) return st;
+  int32_t ncolors = 0;
+  for (int32_t i = 0; i < s; ++i) ncolors = w->color[i] > ncolors ? w->color[i] : ncolors;
+  S->L = L;
+  S->stack = w->stack;
+  S->s = s;
+  S->nw = (s + L - 1) / L;
+  S->B = w->B;
+  S->color = w->color;
+  /* top call: C_B = every local vertex (B_u(u)) */
+  for (int32_t i = 0; i < S->nw; ++i) w->stack[i] = 0;
+  for (int32_t i = 0; i < s; ++i) w->stack[i / L] |= 1u << (i % L);
+  bitcol_list(S, k - 1, w->stack, 0);
+  *ncolors_out = ncolors;
+  *edges_out = ecount;
+  return S->status;
+}
+
 /* BitCol on a DAG (normally the degeneracy DAG).  Per root u: cliques found,
  * work counters, and the features d+_u, number of colors of G_u, |E_u|. */
 int orc_bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, uint64_t* count,
@@ -671,76 +749,54 @@ int orc_bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k
                    int32_t* root_colors, int64_t* root_edges) {
   if (n < 0 || k < 3 || L < 1 || L > 32) return ORC_EINVAL;
   *count = 0;
-  int32_t md = 0;
-  for (int32_t u = 0; u < n; ++u)
-    if (drp[u + 1] - drp[u] > md) md = drp[u + 1] - drp[u];
-  int32_t nwmax = (md + L - 1) / L + 1;
-  uint8_t* adj = (uint8_t*)malloc((size_t)md * (size_t)md + 1);
-  int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * ((size_t)md + 1));
-  int32_t* color = (int32_t*)malloc(sizeof(int32_t) * ((size_t)md + 1));
-  uint32_t* B = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)md + 1) * (size_t)nwmax);
-  uint32_t* stack = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nwmax * ((size_t)k + 2));
-  int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * ((size_t)n + 1));
-  if (!adj || !ids || !color || !B || !stack || !pos) {
-    free(adj); free(ids); free(color); free(B); free(stack); free(pos);
-    return ORC_ENOMEM;
-  }
-  for (int32_t v = 0; v < n; ++v) pos[v] = -1;
+  bitcol_ws_t w;
+  if (bitcol_ws_init(&w, n, drp, k, L)) return ORC_ENOMEM;
   bitcol_t S;
   memset(&S, 0, sizeof(S));
-  S.L = L;
-  S.stack = stack;
   int st = ORC_OK;
   for (int32_t u = 0; u < n && !st; ++u) {
-    int32_t s = drp[u + 1] - drp[u];
-    if (root_count) root_count[u] = 0;
-    if (root_nodes) root_nodes[u] = 0;
-    if (root_isect) root_isect[u] = 0;
-    if (root_words) root_words[u] = 0;
-    if (root_colors) root_colors[u] = 0;
-    if (root_edges) root_edges[u] = 0;
-    if (s < k - 1) continue;
-    /* G_u: induced by N+(u), local index = position in N+(u) */
-    for (int32_t i = 0; i < s; ++i) { ids[i] = dcol[drp[u] + i]; pos[ids[i]] = i; }
-    memset(adj, 0, (size_t)s * (size_t)s);
-    int64_t ecount = 0;
-    for (int32_t i = 0; i < s; ++i) {
-      int32_t v = ids[i];
-      for (int32_t j = drp[v]; j < drp[v + 1]; ++j) {
-        int32_t w = dcol[j];
-        if (pos[w] >= 0) {
-          adj[(size_t)i * s + pos[w]] = 1;
-          adj[(size_t)pos[w] * s + i] = 1;
-          ecount++;
-        }
-      }
-    }
-    for (int32_t i = 0; i < s; ++i) pos[ids[i]] = -1;
-    st = orc_bitcol_encode(s, adj, ids, L, color, B);
-    if (st) break;
-    int32_t ncolors = 0;
-    for (int32_t i = 0; i < s; ++i) ncolors = color[i] > ncolors ? color[i] : ncolors;
-    S.s = s;
-    S.nw = (s + L - 1) / L;
-    S.B = B;
-    S.color = color;
     uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, w0 = S.words;
-    /* top call: C_B = every local vertex (B_u(u)) */
-    for (int32_t i = 0; i < S.nw; ++i) stack[i] = 0;
-    for (int32_t i = 0; i < s; ++i) stack[i / L] |= 1u << (i % L);
-    bitcol_list(&S, k - 1, stack, 0);
-    st = S.status;
+    int32_t nc = 0;
+    int64_t ec = 0;
+    st = bitcol_root(&S, &w, drp, dcol, k, L, u, &nc, &ec);
     if (root_count) root_count[u] = S.count - c0;
     if (root_nodes) root_nodes[u] = S.nodes - n0;
     if (root_isect) root_isect[u] = S.isect - i0;
     if (root_words) root_words[u] = S.words - w0;
-    if (root_colors) root_colors[u] = ncolors;
-    if (root_edges) root_edges[u] = ecount;
+    if (root_colors) root_colors[u] = nc;
+    if (root_edges) root_edges[u] = ec;
   }
-  free(adj); free(ids); free(color); free(B); free(stack); free(pos);
+  bitcol_ws_free(&w);
   if (st) return st;
   *count = S.count;
   return ORC_OK;
+}
+
+/* The same for a list of roots only (sampled checks on large graphs):
+ * entry i of each output describes roots[i]. */
+int orc_bitcol_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, int32_t nroots,
+                     const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                     uint64_t* root_words) {
+  if (n < 0 || k < 3 || L < 1 || L > 32 || nroots < 0) return ORC_EINVAL;
+  for (int32_t i = 0; i < nroots; ++i)
+    if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
+  bitcol_ws_t w;
+  if (bitcol_ws_init(&w, n, drp, k, L)) return ORC_ENOMEM;
+  bitcol_t S;
+  memset(&S, 0, sizeof(S));
+  int st = ORC_OK;
+  for (int32_t i = 0; i < nroots && !st; ++i) {
+    uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, w0 = S.words;
+    int32_t nc = 0;
+    int64_t ec = 0;
+    st = bitcol_root(&S, &w, drp, dcol, k, L, roots[i], &nc, &ec);
+    root_count[i] = S.count - c0;
+    if (root_nodes) root_nodes[i] = S.nodes - n0;
+    if (root_isect) root_isect[i] = S.isect - i0;
+    if (root_words) root_words[i] = S.words - w0;
+  }
+  bitcol_ws_free(&w);
+  return st;
 }
 
 /* ------------------------------------------- whole methods (Alg. 5, 6) */

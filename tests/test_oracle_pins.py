@@ -360,3 +360,19 @@ def test_validate_rejects_bad_csr():
     a_rp, a_ci = asym[0].copy(), asym[1].copy()
     a_ci[0] = 2  # 0 -> 2 without 2 -> 0
     assert not oracle.validate(a_rp, a_ci)
+
+
+def test_bitcol_roots_matches_the_whole_dag_run():
+    """The per-root entry point (used for sampled checks on large graphs)
+    returns exactly the whole-DAG run's per-root values."""
+    g = graphgen.chung_lu(3000, 12.0, 2.1, 300.0, planted=[18, 12], seed=5)
+    for k in (4, 6):
+        rem = oracle.precore(*g, k)
+        rem, _, _, _ = oracle.prelist(*g, k, rem)
+        drp, dci, _, _ = oracle.degeneracy_dag(*g, rem)
+        total, per = oracle.bitcol_dag(drp, dci, k)
+        roots = np.flatnonzero(np.diff(drp) >= k - 1)[::3]
+        sub = oracle.bitcol_roots(drp, dci, k, roots)
+        for key in ("count", "nodes", "isect", "words"):
+            assert np.array_equal(sub[key], per[key][roots]), key
+        assert total == int(per["count"].sum())
