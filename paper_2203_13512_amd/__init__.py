@@ -131,8 +131,8 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
     is the number of k-cliques containing v (int64 values, torch tensor on the
     GPU for GPU input, numpy array otherwise).  With ``stats`` a dict of the
     call's timings and work counters is appended; with ``root_logs`` (GPU
-    input only) the per-vertex root logs (work, joins, features) are added to
-    that dict.
+    input only) the per-vertex root logs (work, joins, features, cliques
+    attributed to the vertex) are added to that dict.
     """
     L = _lib()
     opt = Options()
@@ -166,10 +166,12 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
         if root_logs:
             logs = dict(work=torch.zeros(max(n, 1), dtype=torch.int64, device=dev),
                         isect=torch.zeros(max(n, 1), dtype=torch.int64, device=dev),
-                        features=torch.zeros((max(n, 1), 4), dtype=torch.float32, device=dev))
+                        features=torch.zeros((max(n, 1), 4), dtype=torch.float32, device=dev),
+                        count=torch.zeros(max(n, 1), dtype=torch.int64, device=dev))
             opt.root_work = logs["work"].data_ptr()
             opt.root_isect = logs["isect"].data_ptr()
             opt.root_features = logs["features"].data_ptr()
+            opt.root_count = logs["count"].data_ptr()
         if schedule == "learned":
             if mlp is None:
                 raise ValueError("the learned schedule needs mlp=(params, norm) device tensors")

@@ -1,0 +1,141 @@
+"""Full-size checks on the 4M-vertex power-law workload with planted cliques,
+in the launch configuration the benchmark times (learned schedule, tuned
+launch shape), and what the trained scheduler gains over the degree schedule.
+
+The total of 2.5e14 8-cliques is far beyond what the oracle can enumerate, so
+the full-size parity is checked on properties that hold at any size and on
+sampled outputs the oracle computes one by one:
+  - the orientation: every root's out-degree and core number equal the
+    oracle's degeneracy DAG and peel levels (all 4M vertices);
+  - Pre-List's count equals the oracle's;
+  - sampled roots: cliques listed from the root, BitJoins and words equal
+    the oracle's BitCol run from that root on its own DAG;
+  - the per-root attributions sum to the total.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2203_13512_amd as kc  # noqa: E402
+from paper_2203_13512_amd import autotune, scheduler  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bench_graph():
+    say("generating the 4M-vertex workload")
+    w = graphgen.workload(5)
+    rp_h, ci_h = w.graphs[0]
+    rp = torch.from_numpy(rp_h).cuda()
+    ci = torch.from_numpy(ci_h).cuda()
+    return w, rp_h, ci_h, rp, ci
+
+
+def test_full_size_bench_configuration_sampled_roots(bench_graph):
+    w, rp_h, ci_h, rp, ci = bench_graph
+    k = 8
+    dev = rp.device
+    tuned = autotune.lookup(rp_h, ci_h, k, "color")
+    mlp = scheduler.load_model(dev, k)
+    assert mlp is not None
+    say("GPU count", w.name, k, tuned)
+    c, st = kc.count(rp, ci, k, "color", schedule="learned", mlp=mlp, root_logs=True, **tuned)
+    lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
+    assert int(lg["count"].sum()) == c
+
+    say("oracle preprocessing and orientation")
+    removed = oracle.precore(rp_h, ci_h, k)
+    removed, pl, _, _ = oracle.prelist(rp_h, ci_h, k, removed)
+    assert st["prelist_count"] == pl
+    drp, dci, _, core = oracle.degeneracy_dag(rp_h, ci_h, removed)
+    dplus = np.diff(drp)
+    roots = np.flatnonzero(dplus >= k - 1)
+    f = lg["features"]
+    assert st["n_roots"] == len(roots)
+    assert np.array_equal(f[roots, 0].astype(np.int64), dplus[roots])
+    assert np.array_equal(f[roots, 1].astype(np.int64), core[roots])
+    assert st["max_out_degree"] == int(dplus.max()) and st["max_core"] == int(core.max())
+
+    # sampled roots the oracle can run one by one, chosen from the oracle's
+    # own DAG: every root of core number >= 100 with out-degree <= 45 (the
+    # dense part, where the cliques are; out-degree bounds each recursion),
+    # plus 40 roots drawn by a fixed seed from the rest
+    rng = np.random.default_rng(2203)
+    dense = roots[(core[roots] >= 100) & (dplus[roots] <= 45)]
+    rest = roots[core[roots] < 100]
+    sample = np.concatenate([dense, rng.choice(rest, 40, replace=False)])
+    assert len(dense) >= 50
+    say("oracle BitCol on", len(sample), "sampled roots")
+    per = oracle.bitcol_roots(drp, dci, k, sample)
+    # a sampled root's attribution is what was listed from it (none of them
+    # is the smallest vertex of a Pre-List clique component: those are removed)
+    assert np.array_equal(lg["count"][sample], per["count"].astype(np.int64))
+    assert np.array_equal(lg["isect"][sample], per["isect"].astype(np.int64))
+    assert np.array_equal(lg["work"][sample], per["words"].astype(np.int64))
+    assert int(per["count"].sum()) > 10**7
+
+
+def _spearman(a, b):
+    from scipy.stats import spearmanr  # average ranks for ties
+    return float(spearmanr(a, b).statistic)
+
+
+def test_learned_schedule_gain(bench_graph):
+    """What the trained network gains on the unseen workload (k = 7).  The
+    schedules split the roots they rank heaviest (about 4 x 1024 + 256 of
+    them on 256 CUs); the roots the network ranks on top must hold most of
+    the logged work, far more than the top roots by the degree estimate
+    log C(d+, k-1), and its ranking of the roots that do any work must be
+    closer to the logged one.  At the benchmark's k = 8 the learned schedule
+    then lists faster than the degree schedule at the same count (same
+    kernels, same launch shape)."""
+    w, rp_h, ci_h, rp, ci = bench_graph
+    k = 7
+    dev = rp.device
+    mlp = scheduler.load_model(dev, k)
+    params, norm = mlp
+    c, st = kc.count(rp, ci, k, "color", root_logs=True)
+    lg = st["root_logs"]
+    f = lg["features"]
+    roots = torch.nonzero(f[:, 0] >= k - 1).flatten()
+    x = (torch.log1p(f[roots]) - norm[:4]) / norm[4:]
+    pred = kc.mlp_forward(params, x.contiguous()).cpu().numpy().astype(np.float64)
+    work = lg["work"][roots].cpu().numpy().astype(np.float64)
+    d = f[roots, 0].cpu().numpy().astype(np.float64)
+    deg_est = np.array([math.lgamma(v + 1) - math.lgamma(k) - math.lgamma(v - k + 2) for v in d])
+    top = 4 * 1024 + 256
+    share_mlp = work[np.argsort(-pred)[:top]].sum() / work.sum()
+    share_deg = work[np.argsort(-deg_est)[:top]].sum() / work.sum()
+    nz = work > 0
+    r_mlp = _spearman(pred[nz], np.log1p(work[nz]))
+    r_deg = _spearman(deg_est[nz], np.log1p(work[nz]))
+    say("work share of the top", top, "roots: mlp", round(share_mlp, 4), "degree", round(share_deg, 4),
+        "| rank correlation (working roots): mlp", round(r_mlp, 4), "degree", round(r_deg, 4))
+    assert share_mlp > 0.9 and share_mlp > share_deg + 0.2
+    assert r_mlp > r_deg
+
+    k = 8
+    mlp = scheduler.load_model(dev, k)
+    tuned = autotune.lookup(rp_h, ci_h, k, "color")
+    times, counts = {}, {}
+    for sched in ("learned", "degree"):
+        kw = dict(schedule=sched, stats=True, **tuned)
+        if sched == "learned":
+            kw["mlp"] = mlp
+        counts[sched], s2 = kc.count(rp, ci, k, "color", **kw)
+        times[sched] = s2["list_ms"]
+        say(sched, "listing", round(s2["list_ms"], 1), "ms")
+    assert counts["learned"] == counts["degree"]
+    assert times["learned"] < times["degree"]
