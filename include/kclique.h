@@ -149,6 +149,35 @@ int kclique_count_batched(int32_t num_graphs, const int32_t* n, const int64_t* r
                           const int32_t* row_ptr_cat, const int32_t* col_idx_cat, const int32_t* k, int32_t order,
                           const kc_options* opt, uint64_t* counts_out);
 
+/* ---- prepared batches, replayed as a HIP graph --------------------------
+ * For callers that count the same batch repeatedly, or launch it from a loop
+ * that cannot afford the per-call host work: the preparation (validation,
+ * Pre-Core, Pre-List, orientation, staging, coloring, encoding, scheduling;
+ * Sec. 5-7) runs once, and the listing phase with the per-graph sums is
+ * captured into a HIP graph that every execution replays.  BitCol order only
+ * (KC_ORDER_COLOR; otherwise KC_EUNSUPPORTED).  Arguments as for
+ * kclique_count_batched; the options' schedule, MLP, waves, chunking,
+ * splitting and re-encoding apply (class_streams is forced to 1; per-root
+ * logs and statistics are not produced).  The plan owns its device memory
+ * (the union graph, the staged bitmaps, the queues) until kclique_plan_destroy,
+ * and the caller's graph arrays are not read after kclique_plan_batched
+ * returns.  A plan belongs to the device that was current when it was made. */
+typedef struct kc_plan kc_plan;
+
+int kclique_plan_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off, const int64_t* col_off,
+                         const int32_t* row_ptr_cat, const int32_t* col_idx_cat, const int32_t* k, int32_t order,
+                         const kc_options* opt, kc_plan** plan_out);
+
+/* Replays the plan on `stream` (NULL = default stream) and writes the
+ * per-graph counts to counts_out (device memory if the plan was made with
+ * device_ptrs, else host).  Returns when the counts are written.  Calls on
+ * one plan must not overlap (they share its buffers).  KC_EOVERFLOW as for
+ * kclique_count_batched. */
+int kclique_plan_execute(kc_plan* plan, void* stream, uint64_t* counts_out);
+
+/* Releases the plan's device memory and graph. */
+int kclique_plan_destroy(kc_plan* plan);
+
 /* ---- learned scheduling: MLP 4 -> 64 -> 64 -> 1, ReLU, FP32 -------------
  * Parameter block layout (KC_MLP_NPARAMS floats, row-major):
  *   W1[64][4], b1[64], W2[64][64], b2[64], W3[64] (1 x 64), b3[1].

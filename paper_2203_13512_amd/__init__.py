@@ -90,6 +90,13 @@ def _lib():
     L.kclique_count_ex.argtypes = [i32, vp, vp, i32, i32, ctypes.POINTER(Options), u64p, vp]
     L.kclique_count_batched.restype = ctypes.c_int
     L.kclique_count_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp]
+    L.kclique_plan_batched.restype = ctypes.c_int
+    L.kclique_plan_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(Options),
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    L.kclique_plan_execute.restype = ctypes.c_int
+    L.kclique_plan_execute.argtypes = [vp, vp, vp]
+    L.kclique_plan_destroy.restype = ctypes.c_int
+    L.kclique_plan_destroy.argtypes = [vp]
     L.kc_mlp_forward.restype = ctypes.c_int
     L.kc_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
     L.kc_mlp_train_step.restype = ctypes.c_int
@@ -230,10 +237,7 @@ def per_vertex_host(row_ptr, col_idx, k: int, order: str = "color"):
     return int(out.value), pv[:n]
 
 
-def count_batched(graphs, ks, order: str = "color", **kw):
-    """Counts of many graphs in one call; graphs are (row_ptr, col_idx) host
-    arrays.  Returns a list of counts."""
-    L = _lib()
+def _concat(graphs, ks):
     ns = np.asarray([len(g[0]) - 1 for g in graphs], dtype=np.int32)
     roff = np.zeros(len(graphs), dtype=np.int64)
     coff = np.zeros(len(graphs), dtype=np.int64)
@@ -246,6 +250,14 @@ def count_batched(graphs, ks, order: str = "color", **kw):
                                   else np.zeros(1, np.int32))
     ci_cat = np.ascontiguousarray(np.concatenate([np.asarray(g[1], np.int32) for g in graphs] + [np.zeros(1, np.int32)]))
     kk = np.ascontiguousarray(ks, dtype=np.int32)
+    return ns, roff, coff, rp_cat, ci_cat, kk
+
+
+def count_batched(graphs, ks, order: str = "color", **kw):
+    """Counts of many graphs in one call; graphs are (row_ptr, col_idx) host
+    arrays.  Returns a list of counts."""
+    L = _lib()
+    ns, roff, coff, rp_cat, ci_cat, kk = _concat(graphs, ks)
     out = np.zeros(max(len(graphs), 1), dtype=np.uint64)
     opt = Options()
     L.kc_options_init(ctypes.byref(opt))
@@ -256,6 +268,54 @@ def count_batched(graphs, ks, order: str = "color", **kw):
                                  out.ctypes.data)
     _check(rc, "kclique_count_batched")
     return [int(x) for x in out[:len(graphs)]]
+
+
+class Plan:
+    """A prepared batch (``kclique_plan_batched``): ``execute()`` replays the
+    captured listing phase and returns the per-graph counts; ``close()``
+    releases it."""
+
+    def __init__(self, graphs, ks, order: str = "color", **kw):
+        L = _lib()
+        self._h = ctypes.c_void_p(None)
+        ns, roff, coff, rp_cat, ci_cat, kk = _concat(graphs, ks)
+        self.n = len(graphs)
+        opt = Options()
+        L.kc_options_init(ctypes.byref(opt))
+        keep = []
+        mlp = kw.pop("mlp", None)
+        if kw.get("schedule") is not None:
+            kw["schedule"] = SCHEDULES[kw["schedule"]]
+        if mlp is not None:
+            params, norm = mlp
+            opt.mlp_params, opt.mlp_norm = params.data_ptr(), norm.data_ptr()
+            keep += [params, norm]
+        for key, v in kw.items():
+            setattr(opt, key, v)
+        rc = L.kclique_plan_batched(len(graphs), ns.ctypes.data, roff.ctypes.data, coff.ctypes.data,
+                                    rp_cat.ctypes.data, ci_cat.ctypes.data, kk.ctypes.data, ORDERS[order],
+                                    ctypes.byref(opt), ctypes.byref(self._h))
+        _check(rc, "kclique_plan_batched")
+
+    def execute(self, stream=None):
+        out = np.zeros(max(self.n, 1), dtype=np.uint64)
+        _check(_lib().kclique_plan_execute(self._h, stream, out.ctypes.data), "kclique_plan_execute")
+        return [int(x) for x in out[:self.n]]
+
+    def close(self):
+        if self._h:
+            _lib().kclique_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_batched(graphs, ks, order: str = "color", **kw) -> Plan:
+    return Plan(graphs, ks, order, **kw)
 
 
 # ------------------------------------------------------------------ MLP

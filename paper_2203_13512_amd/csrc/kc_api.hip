@@ -59,12 +59,17 @@ struct HostEvents {
   }
 };
 
+// With `cap` the call is prepared only: everything up to the listing phase
+// runs (in `ext_scr`, which the caller keeps), and the listing phase is handed
+// over in `cap` instead of being launched (BitCol counting only).
 static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
-                      const kc_options* opt_in, uint64_t* count_out, uint64_t* pv_out) {
+                      const kc_options* opt_in, uint64_t* count_out, uint64_t* pv_out,
+                      kc_scratch* ext_scr = nullptr, kc_capture* cap = nullptr) {
   kc_options defaults;
   memset(&defaults, 0, sizeof(defaults));
   const kc_options* opt = opt_in ? opt_in : &defaults;
   if (n < 0 || k < 1 || !count_out) return KC_EINVAL;
+  if (cap && (!ext_scr || order != KC_ORDER_COLOR || pv_out)) return KC_EUNSUPPORTED;
   if (order != KC_ORDER_DEGREE && order != KC_ORDER_COLOR) return KC_EINVAL;
   if (opt->schedule != KC_SCHED_DEGREE && opt->schedule != KC_SCHED_LEARNED) return KC_EINVAL;
   if (n > 0 && !row_ptr) return KC_EINVAL;
@@ -77,7 +82,8 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   for (auto& x : ev.e) KC_HIP(hipEventCreate(&x));
   KC_HIP(hipEventRecord(ev.e[0], s));
 
-  kc_scratch scr(s);
+  kc_scratch local_scr(s);
+  kc_scratch& scr = ext_scr ? *ext_scr : local_scr;
   // ---- graph on the device
   kc_dev_graph g;
   g.n = n;
@@ -143,6 +149,7 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   if (vk && !opt->device_ptrs) return KC_EINVAL;
   if (vk && k < 3) return KC_EUNSUPPORTED;
   if (k <= 2 || (k > n && !vk)) {
+    if (cap) return KC_EUNSUPPORTED;
     // linear cases and the empty answer
     if (k == 1) total = (uint64_t)n;
     else if (k == 2) total = (uint64_t)nnz32 / 2;
@@ -187,9 +194,19 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     c.counters = counters;
     c.opt = opt;
     c.stats = stats;
+    c.capture = cap;
     KC_HIP(hipEventRecord(ev.e[2], s));
     if (order == KC_ORDER_DEGREE) KC_TRY(kc_list_sdegree(c, scr, s));
     else KC_TRY(kc_list_bitcol(c, scr, s));
+    if (cap) {
+      KC_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+      KC_HIP(hipStreamSynchronize(s));
+      if (hflags & KC_FLAG_OVERFLOW) return KC_EOVERFLOW;
+      if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
+      cap->count_d = count_d;
+      cap->flags = flags;
+      return KC_OK;
+    }
     if (stats) {
       stats->n_roots = hr[0];
       stats->max_out_degree = hr[1];
@@ -287,52 +304,50 @@ __global__ void k_graph_sums(int32_t nv, const int32_t* __restrict__ gid, const 
   if (c) atomicAdd(&out[gid[v]], c);
 }
 
-extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off,
-                                     const int64_t* col_off, const int32_t* row_ptr_cat, const int32_t* col_idx_cat,
-                                     const int32_t* k, int32_t order, const kc_options* opt, uint64_t* counts_out) {
-  if (num_graphs < 0 || (num_graphs > 0 && (!n || !row_off || !col_off || !k || !counts_out))) return KC_EINVAL;
-  if (num_graphs == 0) return KC_OK;
-  kc_options o;
-  if (opt) o = *opt;
-  else memset(&o, 0, sizeof(o));
-  hipStream_t s = (hipStream_t)o.stream;
-  const bool dev_in = o.device_ptrs != 0;
-  // sizes (host): vertex and edge offsets of the union, largest k
-  std::vector<int64_t> voff(num_graphs + 1), eoff(num_graphs + 1);
-  std::vector<int32_t> m(num_graphs);
+// The union of a batch of graphs on the device (vertex ids shifted by the
+// preceding graphs' sizes), with each vertex's k (graphs with k < 3 are
+// answered directly and take part with k = 3) and its graph's index.
+struct BatchUnion {
+  int32_t ng = 0;
+  int64_t NV = 0, NE = 0;
   int32_t kmax = 0;
+  std::vector<int32_t> n, m, k;  // per graph: vertices, adjacency entries, requested k
+  int32_t *rp = nullptr, *col = nullptr, *vk = nullptr, *gid = nullptr;
+};
+
+static int build_union(int32_t num_graphs, const int32_t* n, const int64_t* row_off, const int64_t* col_off,
+                       const int32_t* row_ptr_cat, const int32_t* col_idx_cat, const int32_t* k, bool dev_in,
+                       kc_scratch& scr, hipStream_t s, BatchUnion* U) {
+  U->ng = num_graphs;
+  U->n.assign(n, n + num_graphs);
+  U->k.assign(k, k + num_graphs);
+  U->m.assign(num_graphs, 0);
+  std::vector<int64_t> voff(num_graphs + 1), eoff(num_graphs + 1);
+  U->kmax = 0;
   for (int32_t g = 0; g < num_graphs; ++g) {
     if (n[g] < 0 || k[g] < 1) return KC_EINVAL;
     if (dev_in) {
-      KC_HIP(hipMemcpy(&m[g], row_ptr_cat + row_off[g] + n[g], sizeof(int32_t), hipMemcpyDeviceToHost));
+      KC_HIP(hipMemcpy(&U->m[g], row_ptr_cat + row_off[g] + n[g], sizeof(int32_t), hipMemcpyDeviceToHost));
     } else {
-      m[g] = row_ptr_cat[row_off[g] + n[g]];
+      U->m[g] = row_ptr_cat[row_off[g] + n[g]];
     }
-    kmax = k[g] > kmax ? k[g] : kmax;
+    if (U->m[g] < 0) return KC_EINVAL;
+    U->kmax = k[g] > U->kmax ? k[g] : U->kmax;
   }
   voff[0] = eoff[0] = 0;
   for (int32_t g = 0; g < num_graphs; ++g) {
     voff[g + 1] = voff[g] + n[g];
-    eoff[g + 1] = eoff[g] + m[g];
+    eoff[g + 1] = eoff[g] + U->m[g];
   }
-  const int64_t NV = voff[num_graphs], NE = eoff[num_graphs];
-  if (NV >= INT32_MAX || NE >= INT32_MAX) return KC_EUNSUPPORTED;
-  // graphs with k < 3 are answered directly; the rest join the union (their
-  // k must be at least 3 for the listing path), with small k lifted out
-  std::vector<uint64_t> result(num_graphs, 0);
-  bool any_small = false;
-  for (int32_t g = 0; g < num_graphs; ++g)
-    if (k[g] <= 2) any_small = true;
-  kc_scratch scr(s);
-  int32_t *rp_u, *col_u, *vk_u, *gid, *kk_d, *n_d;
+  U->NV = voff[num_graphs];
+  U->NE = eoff[num_graphs];
+  if (U->NV >= INT32_MAX || U->NE >= INT32_MAX) return KC_EUNSUPPORTED;
+  int32_t *kk_d, *n_d;
   int64_t *voff_d, *eoff_d, *roff_d, *coff_d;
-  unsigned long long *rc, *sums;
-  KC_TRY(scr.get(&rp_u, (size_t)NV + 1));
-  KC_TRY(scr.get(&col_u, (size_t)NE + 1));
-  KC_TRY(scr.get(&vk_u, (size_t)NV + 1));
-  KC_TRY(scr.get(&gid, (size_t)NV + 1));
-  KC_TRY(scr.get(&rc, (size_t)NV + 1));
-  KC_TRY(scr.get(&sums, (size_t)num_graphs));
+  KC_TRY(scr.get(&U->rp, (size_t)U->NV + 1));
+  KC_TRY(scr.get(&U->col, (size_t)U->NE + 1));
+  KC_TRY(scr.get(&U->vk, (size_t)U->NV + 1));
+  KC_TRY(scr.get(&U->gid, (size_t)U->NV + 1));
   KC_TRY(scr.get(&kk_d, (size_t)num_graphs));
   KC_TRY(scr.get(&n_d, (size_t)num_graphs));
   KC_TRY(scr.get(&voff_d, (size_t)num_graphs + 1));
@@ -354,7 +369,7 @@ extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const
     int64_t rtot = 0, ctot = 0;
     for (int32_t g = 0; g < num_graphs; ++g) {
       rtot = row_off[g] + n[g] + 1 > rtot ? row_off[g] + n[g] + 1 : rtot;
-      ctot = col_off[g] + m[g] > ctot ? col_off[g] + m[g] : ctot;
+      ctot = col_off[g] + U->m[g] > ctot ? col_off[g] + U->m[g] : ctot;
     }
     int32_t *r_d, *c_d;
     KC_TRY(scr.get(&r_d, (size_t)rtot + 1));
@@ -365,36 +380,196 @@ extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const
     col_src = c_d;
   }
   dim3 grid_r(64, num_graphs), grid_c(256, num_graphs);
-  k_union_rows<<<grid_r, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, eoff_d, rp_src, rp_u, vk_u, kk_d, gid);
-  k_union_cols<<<grid_c, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, coff_d, eoff_d, rp_src, col_src, col_u);
+  k_union_rows<<<grid_r, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, eoff_d, rp_src, U->rp, U->vk, kk_d, U->gid);
+  k_union_cols<<<grid_c, 256, 0, s>>>(num_graphs, n_d, voff_d, roff_d, coff_d, eoff_d, rp_src, col_src, U->col);
   KC_HIP(hipGetLastError());
-  int32_t last = (int32_t)NE;
-  KC_HIP(hipMemcpyAsync(rp_u + NV, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  int32_t last = (int32_t)U->NE;
+  KC_HIP(hipMemcpyAsync(U->rp + U->NV, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
   KC_HIP(hipStreamSynchronize(s));
+  return KC_OK;
+}
+
+// Options of the union's call: per-vertex k and per-root attribution.
+static kc_options union_options(const kc_options& o, const BatchUnion& U, unsigned long long* rc) {
   kc_options u = o;
   u.device_ptrs = 1;
-  u.vertex_k = vk_u;
+  u.vertex_k = U.vk;
   u.root_count = (uint64_t*)rc;
   u.root_work = nullptr;
   u.root_isect = nullptr;
   u.root_features = nullptr;
-  uint64_t total = 0;
-  KC_TRY(count_impl((int32_t)NV, rp_u, col_u, kmax < 3 ? 3 : kmax, order, &u, &total, nullptr));
-  KC_HIP(hipMemsetAsync(sums, 0, sizeof(unsigned long long) * num_graphs, s));
-  k_graph_sums<<<(unsigned)((NV + 255) / 256), 256, 0, s>>>((int32_t)NV, gid, rc, sums);
-  KC_HIP(hipGetLastError());
-  KC_HIP(hipMemcpyAsync(result.data(), sums, sizeof(uint64_t) * num_graphs, hipMemcpyDeviceToHost, s));
-  KC_HIP(hipStreamSynchronize(s));
-  // k = 1 and k = 2 directly
-  if (any_small)
-    for (int32_t g = 0; g < num_graphs; ++g)
-      if (k[g] == 1) result[g] = (uint64_t)n[g];
-      else if (k[g] == 2) result[g] = (uint64_t)m[g] / 2;
-  if (dev_in) {
-    KC_HIP(hipMemcpyAsync(counts_out, result.data(), sizeof(uint64_t) * num_graphs, hipMemcpyHostToDevice, s));
+  u.stats = nullptr;
+  return u;
+}
+
+// Per-graph results: the union's per-graph sums, with k = 1 and k = 2 answered
+// directly; written to host or device memory.
+static int finish_batch(const BatchUnion& U, const uint64_t* sums_host, bool dev_out, uint64_t* counts_out,
+                        hipStream_t s) {
+  std::vector<uint64_t> result(sums_host, sums_host + U.ng);
+  for (int32_t g = 0; g < U.ng; ++g)
+    if (U.k[g] == 1) result[g] = (uint64_t)U.n[g];
+    else if (U.k[g] == 2) result[g] = (uint64_t)U.m[g] / 2;
+  if (dev_out) {
+    KC_HIP(hipMemcpyAsync(counts_out, result.data(), sizeof(uint64_t) * U.ng, hipMemcpyHostToDevice, s));
     KC_HIP(hipStreamSynchronize(s));
   } else {
-    memcpy(counts_out, result.data(), sizeof(uint64_t) * num_graphs);
+    memcpy(counts_out, result.data(), sizeof(uint64_t) * U.ng);
   }
+  return KC_OK;
+}
+
+extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off,
+                                     const int64_t* col_off, const int32_t* row_ptr_cat, const int32_t* col_idx_cat,
+                                     const int32_t* k, int32_t order, const kc_options* opt, uint64_t* counts_out) {
+  if (num_graphs < 0 || (num_graphs > 0 && (!n || !row_off || !col_off || !k || !counts_out))) return KC_EINVAL;
+  if (num_graphs == 0) return KC_OK;
+  kc_options o;
+  if (opt) o = *opt;
+  else memset(&o, 0, sizeof(o));
+  hipStream_t s = (hipStream_t)o.stream;
+  const bool dev_in = o.device_ptrs != 0;
+  kc_scratch scr(s);
+  BatchUnion U;
+  KC_TRY(build_union(num_graphs, n, row_off, col_off, row_ptr_cat, col_idx_cat, k, dev_in, scr, s, &U));
+  unsigned long long *rc, *sums;
+  KC_TRY(scr.get(&rc, (size_t)U.NV + 1));
+  KC_TRY(scr.get(&sums, (size_t)num_graphs));
+  kc_options u = union_options(o, U, rc);
+  uint64_t total = 0;
+  KC_TRY(count_impl((int32_t)U.NV, U.rp, U.col, U.kmax < 3 ? 3 : U.kmax, order, &u, &total, nullptr));
+  KC_HIP(hipMemsetAsync(sums, 0, sizeof(unsigned long long) * num_graphs, s));
+  k_graph_sums<<<(unsigned)((U.NV + 255) / 256), 256, 0, s>>>((int32_t)U.NV, U.gid, rc, sums);
+  KC_HIP(hipGetLastError());
+  std::vector<uint64_t> hs(num_graphs);
+  KC_HIP(hipMemcpyAsync(hs.data(), sums, sizeof(uint64_t) * num_graphs, hipMemcpyDeviceToHost, s));
+  KC_HIP(hipStreamSynchronize(s));
+  return finish_batch(U, hs.data(), dev_in, counts_out, s);
+}
+
+// ------------------------------------------------------------ plans
+// A prepared batch: preprocessing, orientation, staging and scheduling ran
+// once; the listing phase and the per-graph sums are a captured HIP graph that
+// each execution replays.  The graph starts by restoring the state the
+// listing phase starts from (totals and flags cleared, per-root attribution
+// back to the Pre-List part), with kernels only.
+__global__ void k_plan_reset(unsigned long long* count_d, int* flags, unsigned long long* rc,
+                             const unsigned long long* __restrict__ rc_pre, int64_t nv, unsigned long long* sums,
+                             int32_t ng) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < nv; i += stride) rc[i] = rc_pre[i];
+  for (int64_t i = i0; i < ng; i += stride) sums[i] = 0;
+  if (i0 == 0) {
+    count_d[0] = 0;
+    for (int j = 0; j < 4; ++j) flags[j] = 0;
+  }
+}
+
+struct kc_plan {
+  int device = 0;
+  hipStream_t cs = nullptr;  // capture stream
+  kc_scratch* scr = nullptr;
+  kc_capture cap;
+  BatchUnion U;
+  unsigned long long *rc = nullptr, *rc_pre = nullptr, *sums = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dev_out = false;
+  ~kc_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamSynchronize(cs);
+    delete scr;  // frees on its stream
+    if (cs) {
+      (void)hipStreamSynchronize(cs);
+      (void)hipStreamDestroy(cs);
+    }
+  }
+};
+
+static int plan_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off, const int64_t* col_off,
+                        const int32_t* row_ptr_cat, const int32_t* col_idx_cat, const int32_t* k, int32_t order,
+                        const kc_options* opt, kc_plan* P) {
+  kc_options o;
+  if (opt) o = *opt;
+  else memset(&o, 0, sizeof(o));
+  const bool dev_in = o.device_ptrs != 0;
+  P->dev_out = dev_in;
+  KC_HIP(hipGetDevice(&P->device));
+  KC_HIP(hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking));
+  hipStream_t s = P->cs;
+  o.stream = (void*)s;
+  P->scr = new kc_scratch(s);
+  KC_TRY(build_union(num_graphs, n, row_off, col_off, row_ptr_cat, col_idx_cat, k, dev_in, *P->scr, s, &P->U));
+  const BatchUnion& U = P->U;
+  KC_TRY(P->scr->get(&P->rc, (size_t)U.NV + 1));
+  KC_TRY(P->scr->get(&P->rc_pre, (size_t)U.NV + 1));
+  KC_TRY(P->scr->get(&P->sums, (size_t)num_graphs));
+  kc_options u = union_options(o, U, P->rc);
+  u.class_streams = 1;  // one stream: the replay is a chain of kernels
+  uint64_t unused = 0;
+  KC_TRY(count_impl((int32_t)U.NV, U.rp, U.col, U.kmax < 3 ? 3 : U.kmax, order, &u, &unused, nullptr, P->scr,
+                    &P->cap));
+  // the attribution so far is Pre-List's; every replay starts from it
+  KC_HIP(hipMemcpyAsync(P->rc_pre, P->rc, sizeof(unsigned long long) * (size_t)U.NV, hipMemcpyDeviceToDevice, s));
+  KC_HIP(hipStreamSynchronize(s));
+  KC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int st = KC_OK;
+  {
+    const int64_t nv = U.NV > num_graphs ? U.NV : num_graphs;
+    const unsigned blocks = (unsigned)((nv + 255) / 256 < 4096 ? (nv + 255) / 256 : 4096);
+    k_plan_reset<<<blocks > 0 ? blocks : 1, 256, 0, s>>>(P->cap.count_d, P->cap.flags, P->rc, P->rc_pre, U.NV,
+                                                         P->sums, num_graphs);
+    if (P->cap.launch) st = P->cap.launch(P->cap.state, s);
+    if (st == KC_OK && U.NV > 0)
+      k_graph_sums<<<(unsigned)((U.NV + 255) / 256), 256, 0, s>>>((int32_t)U.NV, U.gid, P->rc, P->sums);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  P->graph = g;
+  if (st != KC_OK) return st;
+  KC_HIP(e);
+  KC_HIP(hipGetLastError());
+  KC_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  return KC_OK;
+}
+
+extern "C" int kclique_plan_batched(int32_t num_graphs, const int32_t* n, const int64_t* row_off,
+                                    const int64_t* col_off, const int32_t* row_ptr_cat, const int32_t* col_idx_cat,
+                                    const int32_t* k, int32_t order, const kc_options* opt, kc_plan** plan_out) {
+  if (!plan_out) return KC_EINVAL;
+  *plan_out = nullptr;
+  if (num_graphs < 1 || !n || !row_off || !col_off || !k || !row_ptr_cat) return KC_EINVAL;
+  if (order != KC_ORDER_COLOR) return KC_EUNSUPPORTED;
+  kc_plan* P = new kc_plan;
+  const int st = plan_batched(num_graphs, n, row_off, col_off, row_ptr_cat, col_idx_cat, k, order, opt, P);
+  if (st != KC_OK) {
+    delete P;
+    return st;
+  }
+  *plan_out = P;
+  return KC_OK;
+}
+
+extern "C" int kclique_plan_execute(kc_plan* P, void* stream, uint64_t* counts_out) {
+  if (!P || !counts_out || !P->exec) return KC_EINVAL;
+  int dev = -1;
+  KC_HIP(hipGetDevice(&dev));
+  if (dev != P->device) return KC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  KC_HIP(hipGraphLaunch(P->exec, s));
+  std::vector<uint64_t> hs(P->U.ng);
+  int hflags = 0;
+  KC_HIP(hipMemcpyAsync(hs.data(), P->sums, sizeof(uint64_t) * P->U.ng, hipMemcpyDeviceToHost, s));
+  KC_HIP(hipMemcpyAsync(&hflags, P->cap.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  KC_HIP(hipStreamSynchronize(s));
+  if (hflags & KC_FLAG_OVERFLOW) return KC_EOVERFLOW;
+  if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
+  return finish_batch(P->U, hs.data(), P->dev_out, counts_out, s);
+}
+
+extern "C" int kclique_plan_destroy(kc_plan* P) {
+  delete P;
   return KC_OK;
 }

@@ -1517,8 +1517,18 @@ static size_t device_max_lds() {
   return (size_t)v;
 }
 
+// A resolved listing launch: kernel instance, grid and LDS size.  Resolving
+// sets the kernel's LDS attribute and queries its occupancy, so a captured
+// launch sequence makes no such calls while the stream is being captured.
+struct ListLaunch {
+  const void* fn = nullptr;
+  int64_t grid = 0;
+  int threads = 0;
+  size_t bytes = 0;
+};
+
 template <int W, int NW, bool PV>
-static int launch_list(const ListArgs& a, hipStream_t st) {
+static int resolve_list(const ListArgs& a, ListLaunch* L) {
   const bool comp = a.cmax > 0;
   const size_t bytes = list_lds_bytes<W, NW, PV>(a);
   auto fn = comp ? k_bitcol_list<W, NW, PV, true> : k_bitcol_list<W, NW, PV, false>;
@@ -1529,25 +1539,27 @@ static int launch_list(const ListArgs& a, hipStream_t st) {
   int64_t grid = (int64_t)per_cu * kc_device_cus();
   if (grid > a.ntasks) grid = a.ntasks;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 * NW), bytes, st, a);
-  KC_HIP(hipGetLastError());
+  L->fn = (const void*)fn;
+  L->grid = grid;
+  L->threads = 64 * NW;
+  L->bytes = bytes;
   return KC_OK;
 }
 
 template <int W, bool PV>
-static int launch_list_nw(const ListArgs& a, int nw, hipStream_t st) {
+static int resolve_list_nw(const ListArgs& a, int nw, ListLaunch* L) {
   // fewer waves per root when the requested shape's LDS does not fit
   const size_t lim = device_max_lds();
-  if (nw >= 8 && list_lds_bytes<W, 8, PV>(a) <= lim) return launch_list<W, 8, PV>(a, st);
-  if (nw >= 2 && list_lds_bytes<W, 4, PV>(a) <= lim) return launch_list<W, 4, PV>(a, st);
-  if (list_lds_bytes<W, 1, PV>(a) <= lim) return launch_list<W, 1, PV>(a, st);
+  if (nw >= 8 && list_lds_bytes<W, 8, PV>(a) <= lim) return resolve_list<W, 8, PV>(a, L);
+  if (nw >= 2 && list_lds_bytes<W, 4, PV>(a) <= lim) return resolve_list<W, 4, PV>(a, L);
+  if (list_lds_bytes<W, 1, PV>(a) <= lim) return resolve_list<W, 1, PV>(a, L);
   return KC_EUNSUPPORTED;
 }
 
-static int launch_list_class(const ListArgs& a, int cls, int nw, bool pv, hipStream_t st) {
+static int resolve_list_class(const ListArgs& a, int cls, int nw, bool pv, ListLaunch* L) {
 #define KC_CASE(c, W)                                                            \
   case c:                                                                        \
-    return pv ? launch_list_nw<W, true>(a, nw, st) : launch_list_nw<W, false>(a, nw, st);
+    return pv ? resolve_list_nw<W, true>(a, nw, L) : resolve_list_nw<W, false>(a, nw, L);
   switch (cls) {
     KC_CASE(0, 1)
     KC_CASE(1, 2)
@@ -1557,14 +1569,59 @@ static int launch_list_class(const ListArgs& a, int cls, int nw, bool pv, hipStr
     KC_CASE(5, 16)
     case 6:
       if (pv) return KC_EUNSUPPORTED;
-      return launch_list_nw<24, false>(a, nw, st);
+      return resolve_list_nw<24, false>(a, nw, L);
     case 7:
       if (pv) return KC_EUNSUPPORTED;
-      return launch_list_nw<32, false>(a, nw, st);
+      return resolve_list_nw<32, false>(a, nw, L);
   }
 #undef KC_CASE
   return KC_EUNSUPPORTED;
 }
+
+static int run_list(const ListLaunch& L, const ListArgs& a, hipStream_t st) {
+  ListArgs arg = a;
+  void* args[] = {(void*)&arg};
+  KC_HIP(hipLaunchKernel(L.fn, dim3((unsigned)L.grid), dim3((unsigned)L.threads), args, L.bytes, st));
+  return KC_OK;
+}
+
+static int launch_list_class(const ListArgs& a, int cls, int nw, bool pv, hipStream_t st) {
+  ListLaunch L;
+  KC_TRY(resolve_list_class(a, cls, nw, pv, &L));
+  return run_list(L, a, st);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// The listing phase of a prepared call, replayable: the queue heads and the
+// per-class counters are cleared by a kernel (not a memset), the classes'
+// kernels follow each other on one stream, and the counters are added to the
+// call's totals.
+struct BitcolReplay {
+  ListArgs la[KC_NCLASS];
+  ListLaunch ll[KC_NCLASS];
+  bool used[KC_NCLASS] = {};
+  unsigned long long* heads = nullptr;
+  unsigned long long* cls_ctr = nullptr;
+  unsigned long long* counters = nullptr;
+};
+
+static int bitcol_replay_launch(const void* state, hipStream_t st) {
+  const BitcolReplay& R = *(const BitcolReplay*)state;
+  k_fill_u64<<<1, 64, 0, st>>>(R.heads, KC_NCLASS, 0ull);
+  k_fill_u64<<<1, 64, 0, st>>>(R.cls_ctr, KC_NCTR * KC_NCLASS, 0ull);
+  KC_HIP(hipGetLastError());
+  for (int cl = KC_NCLASS - 1; cl >= 0; --cl)
+    if (R.used[cl]) KC_TRY(run_list(R.ll[cl], R.la[cl], st));
+  k_add_counters<<<1, 64, 0, st>>>(R.cls_ctr, KC_NCLASS, R.counters);
+  KC_HIP(hipGetLastError());
+  return KC_OK;
+}
+
+static void bitcol_replay_destroy(void* state) { delete (BitcolReplay*)state; }
 
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
@@ -1797,12 +1854,66 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   // ---- listing: one persistent launch per bitmap class, heaviest first
   unsigned long long* heads;
   KC_TRY(scr.get(&heads, KC_NCLASS));
+  unsigned long long* cls_ctr;
+  KC_TRY(scr.get(&cls_ctr, KC_NCTR * KC_NCLASS));
+  ListArgs las[KC_NCLASS];
+  int nws[KC_NCLASS];
+  for (int cl = 0; cl < KC_NCLASS; ++cl) {
+    int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
+    ListArgs& la = las[cl];
+    la.roots = c.roots;
+    la.ri = ri;
+    la.B = B;
+    la.Bin = Bin;
+    la.perm = perm;
+    la.color = color;
+    la.tasks = tasks_sorted + lo;
+    la.ntasks = hi - lo;
+    la.head = heads + cl;
+    nws[cl] = opt && opt->waves_per_root > 0 ? opt->waves_per_root : (kWClass[cl] >= 8 ? 4 : 1);
+    la.chunk = opt && opt->chunk > 0 ? opt->chunk : (kWClass[cl] >= 8 ? 1 : 8);
+    la.k = c.k;
+    la.vk = c.vk;
+    la.root_count = c.root_count;
+    {
+      const int cap = pv ? 64 : 128;  // two-word re-encoding only when counting
+      const int want = opt ? opt->compress : 0;  // 0 = auto: the cap; < 0 = off
+      la.cmax = want == 0 ? cap : (want < 0 ? 0 : (want > cap ? cap : want));
+    }
+    la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
+    la.count = c.count;
+    la.pv = c.pv;
+    la.counters = cls_ctr + KC_NCTR * cl;
+    la.root_work = c.root_work;
+    la.root_isect = c.root_isect;
+    la.flags = c.flags;
+  }
+  if (c.capture) {
+    // a prepared call: hand the listing phase over to be captured and replayed
+    BitcolReplay* rp = new BitcolReplay;
+    rp->heads = heads;
+    rp->cls_ctr = cls_ctr;
+    rp->counters = c.counters;
+    for (int cl = 0; cl < KC_NCLASS; ++cl) {
+      rp->la[cl] = las[cl];
+      rp->used[cl] = las[cl].ntasks > 0;
+      if (rp->used[cl]) {
+        const int st2 = resolve_list_class(las[cl], cl, nws[cl], pv, &rp->ll[cl]);
+        if (st2 != KC_OK) {
+          delete rp;
+          return st2;
+        }
+      }
+    }
+    c.capture->state = rp;
+    c.capture->launch = bitcol_replay_launch;
+    c.capture->destroy = bitcol_replay_destroy;
+    return KC_OK;
+  }
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * KC_NCLASS, st));
   KC_HIP(hipEventRecord(ev_list.a, st));
   int launches = 0;
   EventPair ev_cls[KC_NCLASS];
-  unsigned long long* cls_ctr;
-  KC_TRY(scr.get(&cls_ctr, KC_NCTR * KC_NCLASS));
   KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * KC_NCTR * KC_NCLASS, st));
   // One persistent kernel per word class, heaviest class first.  They either
   // follow each other on the call's stream, or run concurrently on streams of
@@ -1826,8 +1937,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   struct EvGuard { hipEvent_t e; ~EvGuard() { (void)hipEventDestroy(e); } } ready_guard{ready};
   KC_HIP(hipEventRecord(ready, st));
   for (int cl = KC_NCLASS - 1; cl >= 0; --cl) {
-    int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
-    if (hi <= lo) continue;
+    if (las[cl].ntasks <= 0) continue;
     hipStream_t ls = st;
     if (cmode == 2) {
       KC_HIP(hipStreamCreateWithFlags(&cs.s[cl], hipStreamNonBlocking));
@@ -1837,35 +1947,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     }
     KC_TRY(ev_cls[cl].init());
     KC_HIP(hipEventRecord(ev_cls[cl].a, ls));
-    ListArgs la;
-    la.roots = c.roots;
-    la.ri = ri;
-    la.B = B;
-    la.Bin = Bin;
-    la.perm = perm;
-    la.color = color;
-    la.tasks = tasks_sorted + lo;
-    la.ntasks = hi - lo;
-    la.head = heads + cl;
-    int nw = opt && opt->waves_per_root > 0 ? opt->waves_per_root : (kWClass[cl] >= 8 ? 4 : 1);
-    int chunk = opt && opt->chunk > 0 ? opt->chunk : (kWClass[cl] >= 8 ? 1 : 8);
-    la.chunk = chunk;
-    la.k = c.k;
-    la.vk = c.vk;
-    la.root_count = c.root_count;
-    {
-      const int cap = pv ? 64 : 128;  // two-word re-encoding only when counting
-      const int want = opt ? opt->compress : 0;  // 0 = auto: the cap; < 0 = off
-      la.cmax = want == 0 ? cap : (want < 0 ? 0 : (want > cap ? cap : want));
-    }
-    la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
-    la.count = c.count;
-    la.pv = c.pv;
-    la.counters = cls_ctr + KC_NCTR * cl;
-    la.root_work = c.root_work;
-    la.root_isect = c.root_isect;
-    la.flags = c.flags;
-    KC_TRY(launch_list_class(la, cl, nw, pv, ls));
+    KC_TRY(launch_list_class(las[cl], cl, nws[cl], pv, ls));
     KC_HIP(hipEventRecord(ev_cls[cl].b, ls));
     if (cmode == 2) {
       KC_HIP(hipEventRecord(cs.done[cl], ls));

@@ -120,7 +120,7 @@ struct kc_dev_graph {
 // Stream-ordered scratch allocation that is released at scope exit.
 struct kc_scratch {
   hipStream_t stream = nullptr;
-  void* ptrs[64];
+  void* ptrs[128];
   int count = 0;
   explicit kc_scratch(hipStream_t s) : stream(s) {}
   ~kc_scratch();
@@ -173,6 +173,20 @@ struct kc_list_ctx {
   unsigned long long* counters;
   const kc_options* opt;
   kc_stats* stats;
+  struct kc_capture* capture;  // non-null: prepare only, hand the listing phase over
+};
+
+// A prepared call's listing phase, to be captured into a HIP graph and
+// replayed: `launch` enqueues it on a stream (kernels only).
+struct kc_capture {
+  unsigned long long* count_d = nullptr;  // the call's device total (listing part)
+  int* flags = nullptr;                   // the call's device flags
+  void* state = nullptr;
+  int (*launch)(const void* state, hipStream_t s) = nullptr;
+  void (*destroy)(void* state) = nullptr;
+  ~kc_capture() {
+    if (destroy && state) destroy(state);
+  }
 };
 int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t s);
 int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t s);

@@ -31,7 +31,7 @@ kc_scratch::~kc_scratch() {
   for (int i = 0; i < count; ++i) (void)hipFreeAsync(ptrs[i], stream);
 }
 int kc_scratch::alloc(void** p, size_t bytes) {
-  if (count >= 64) return KC_ENOMEM;
+  if (count >= 128) return KC_ENOMEM;
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMallocAsync(p, bytes, stream);
   if (e != hipSuccess) {

@@ -305,6 +305,35 @@ def test_batched_counts_equal_single_runs():
             assert c == oracle.count(*g, k), (k, order)
 
 
+def test_plan_replays_equal_eager_and_oracle():
+    """A prepared batch replayed as a captured HIP graph: every replay, with
+    the program's own eager GPU work and synchronizations in between, equals
+    the eager batched call and the oracle, graph by graph."""
+    w = graphgen.workload(4, scale=0.03)
+    ks = list(w.ks)
+    ks[0], ks[1] = 1, 2
+    want = [oracle.count(*g, k) for g, k in zip(w.graphs, ks)]
+    assert kc.count_batched(w.graphs, ks, "color") == want
+    from paper_2203_13512_amd import scheduler
+    for kw in [dict(), dict(schedule="learned", mlp=scheduler.load_model(torch.device("cuda"), 8), waves_per_root=8),
+               dict(compress=-1, split=2, split_threshold=1.0)]:
+        say("plan", len(w.graphs), {key: v for key, v in kw.items() if key != "mlp"})
+        plan = kc.plan_batched(w.graphs, ks, "color", **kw)
+        try:
+            for i in range(3):
+                assert plan.execute() == want, (kw, i)
+                x = torch.randn(1 << 20, device="cuda")
+                assert float((x * 0).sum().item()) == 0.0
+                torch.cuda.synchronize()
+                assert kc.count_batched(w.graphs[:6], ks[:6], "color") == want[:6]
+        finally:
+            plan.close()
+    # an overflow is reported when the plan is made
+    with pytest.raises(kc.KCliqueError) as e:
+        kc.plan_batched([G.complete(201)], [20], "color")
+    assert e.value.status == kc.EOVERFLOW
+
+
 def test_root_attribution_sums_to_the_total():
     g = graphgen.chung_lu(4000, 12.0, 2.1, 400.0, planted=[20, 12], seed=21)
     g = G.disjoint_union([g, G.complete(9), G.complete(5)])
