@@ -35,8 +35,8 @@ INT32_VALU_PEAK_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_HZ / 1e12
 # 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE x
 # 2.000 and WRITE_SIZE x 1.000, factors from a plain 1 GiB copy), valid only
 # for the kernel sources they were taken on.
-PROFILED_TRAFFIC = {"sources_sha256_16": "ecf300f862fe73bf", "word_class": 16,
-                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.45e9,
+PROFILED_TRAFFIC = {"sources_sha256_16": "18e5b7998d7ebe7e", "word_class": 16,
+                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.70e9,
                     "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md"}
 
 
