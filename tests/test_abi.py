@@ -11,6 +11,7 @@ import paper_2203_13512_amd as kc
 def test_header_declares_the_boundary():
     names = kc.declared_symbols()
     for f in ["kclique_count", "kclique_list_per_vertex", "kclique_count_ex", "kclique_count_batched",
+              "kclique_plan_batched", "kclique_plan_execute", "kclique_plan_destroy",
               "kc_mlp_forward", "kc_mlp_train_step", "kc_status_string", "kc_options_init"]:
         assert f in names
 
@@ -43,3 +44,24 @@ def test_binding_refuses_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(kc, "_LIB", None)
     with pytest.raises(RuntimeError):
         kc._lib()
+
+
+def _header_fields(struct_name):
+    import re
+    text = open(kc.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{((?:(?!typedef struct).)*?)\}\s*" + struct_name + r"\s*;", text,
+                     flags=re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.search(r"\**\s*(\w+)\s*(\[\d+\])?$", decl)
+        names.append(m.group(1))
+    return names
+
+
+def test_binding_structs_follow_the_header_field_order():
+    assert [f[0] for f in kc.Options._fields_] == _header_fields("kc_options")
+    assert [f[0] for f in kc.Stats._fields_] == _header_fields("kc_stats")
