@@ -12,7 +12,10 @@
 // join touches only the range where matches can occur.  At l = 2 the hits
 // are only counted.  Pruning follows Alg. 5: x is skipped when d+_x <= l-2,
 // and a child list is entered only when it holds more than l-2 members.
-// Work is logged as |C| + d+_x per join, the cost term of Lemma 2.
+// Work is logged as |C| + d+_x per join, the cost term of Lemma 2.  When
+// counting, the joins of a level-2 node run lane-parallel instead (one
+// candidate per lane, each walking its own N+(x)), so that their memory
+// latencies overlap.
 #include <hip/hip_runtime.h>
 
 #include <stdio.h>
@@ -88,7 +91,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   const int lane = threadIdx.x;
   __shared__ int32_t sh_task[2];
 
-  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;
+  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;  // per lane; summed over the wave per task
   for (;;) {
     if (lane == 0) {
       unsigned long long t = atomicAdd(a.head, (unsigned long long)a.chunk);
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
         tot[0] = 0;
       }
       __syncthreads();
-      my_nodes++;
+      my_nodes += (lane == 0);
       const int L0 = kt - 1;
       int d = 0;
       for (;;) {
@@ -138,6 +141,44 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           continue;
         }
         int32_t* C = list + (size_t)d * SM;
+        if (!PV && l == 2) {
+          // A level-2 node, lane-parallel: lane i takes candidate C[c + i]
+          // (and every 64th after it) and counts |N+(x) ∩ C| on its own,
+          // walking N+(x) within [min C, max C] with a moving binary search
+          // in C.  Same pruning, joins and work as the wave-wide join.
+          const int32_t cmin = C[0], cmax = C[sz - 1];
+          uint64_t node_total = 0;
+          for (int idx = c + lane; idx < sz; idx += 64) {
+            const int32_t x = C[idx];
+            const int32_t xb = a.drp[x], xe = a.drp[x + 1];
+            const int dx = xe - xb;
+            if (dx <= 0) continue;
+            my_isect++;
+            my_work += (uint64_t)sz + (uint64_t)dx;
+            int lo = xb, hi = xe;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (a.dcol[mid] < cmin) lo = mid + 1; else hi = mid;
+            }
+            int q = 0;
+            uint32_t hits = 0;
+            for (int i = lo; i < xe; ++i) {
+              const int32_t y = a.dcol[i];
+              if (y > cmax) break;
+              q = sd_lower_bound(C, q, sz, y);
+              if (q >= sz) break;
+              hits += C[q] == y;
+            }
+            node_total += hits;
+          }
+          const uint64_t T2 = kc_wave_sum_u64(node_total);
+          if (lane == 0) {
+            tot[d] += (unsigned long long)T2;
+            cur[d] = sz;
+          }
+          kc_wave_lds_sync();
+          continue;
+        }
         const int32_t x = C[c];
         const int xi = PV ? lidx[(size_t)d * SM + c] : 0;
         if (lane == 0) cur[d] = c + 1;
@@ -145,8 +186,8 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
         const int32_t xb = a.drp[x], xe = a.drp[x + 1];
         const int dx = xe - xb;
         if (dx <= l - 2) continue;
-        my_isect++;
-        my_work += (uint64_t)sz + (uint64_t)dx;
+        my_isect += (lane == 0);
+        my_work += lane == 0 ? (uint64_t)sz + (uint64_t)dx : 0u;
         // merge join N+(x) with C
         const int32_t cmin = C[0], cmax = C[sz - 1];
         // first entry of N+(x) that can match
@@ -203,7 +244,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           }
           kc_wave_lds_sync();
           d++;
-          my_nodes++;
+          my_nodes += (lane == 0);
         }
       }
       __syncthreads();
@@ -218,12 +259,16 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           unsigned long long cc = cnt[i];
           if (cc) kc_add_checked(&a.pv[a.dcol[b0 + i]], cc, a.flags);
         }
-      if (lane == 0) {
-        if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)my_isect);
-        if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)my_work);
-        atomicAdd(&a.counters[0], (unsigned long long)my_nodes);
-        atomicAdd(&a.counters[1], (unsigned long long)my_isect);
-        atomicAdd(&a.counters[2], (unsigned long long)my_work);
+      {
+        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work),
+                       wn = kc_wave_sum_u64(my_nodes);
+        if (lane == 0) {
+          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+          if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
+          atomicAdd(&a.counters[0], (unsigned long long)wn);
+          atomicAdd(&a.counters[1], (unsigned long long)wi);
+          atomicAdd(&a.counters[2], (unsigned long long)ww);
+        }
       }
       my_nodes = my_isect = my_work = 0;
       __syncthreads();
