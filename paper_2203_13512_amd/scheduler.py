@@ -108,8 +108,10 @@ def train(X: np.ndarray, y: np.ndarray, device, steps: int = 4000, batch: int = 
 
 
 def spearman(a: np.ndarray, b: np.ndarray) -> float:
-    ra = np.argsort(np.argsort(a)).astype(np.float64)
-    rb = np.argsort(np.argsort(b)).astype(np.float64)
+    """Spearman rank correlation (average ranks for ties)."""
+    from scipy.stats import rankdata
+    ra = rankdata(a).astype(np.float64)
+    rb = rankdata(b).astype(np.float64)
     ra -= ra.mean()
     rb -= rb.mean()
     return float((ra * rb).sum() / math.sqrt((ra * ra).sum() * (rb * rb).sum()))

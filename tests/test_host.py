@@ -1,0 +1,86 @@
+"""Host-side logic that needs no GPU: the autotuner's cache keys, the saved
+scheduler model, the benchmark's argument contract and the generators'
+determinism and recipes."""
+import json
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_2203_13512_amd as kc
+from paper_2203_13512_amd import autotune, scheduler
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_autotune_signature_is_stable_and_keyed(tmp_path):
+    g = graphgen.chung_lu(2000, 8.0, 2.1, 200.0, seed=1)
+    s = autotune.signature(*g, 5, "color")
+    assert s == autotune.signature(*g, 5, "color")
+    assert s != autotune.signature(*g, 6, "color")
+    assert s != autotune.signature(*g, 5, "degree")
+    h = graphgen.chung_lu(2000, 8.0, 2.1, 200.0, seed=2)
+    assert s != autotune.signature(*h, 5, "color")
+    assert autotune.lookup(*g, 5, "color", path=str(tmp_path / "none.json")) == {}
+    cache = tmp_path / "c.json"
+    cache.write_text(json.dumps({s: {"best": {"waves_per_root": 8}}}))
+    assert autotune.lookup(*g, 5, "color", path=str(cache)) == {"waves_per_root": 8}
+
+
+def test_autotune_cache_holds_launch_options_only():
+    fields = {f[0] for f in kc.Options._fields_}
+    for key, e in autotune.load_cache().items():
+        assert set(e["best"]) <= fields, e["best"]
+        assert e["order"] in kc.ORDERS and e["k"] >= 3
+        for cand in autotune.SPACE:
+            assert set(cand) <= fields
+
+
+def test_saved_scheduler_model_matches_the_network():
+    with open(scheduler.MODEL_PATH) as f:
+        models = json.load(f)["models"]
+    assert models
+    for k, m in models.items():
+        assert len(m["params"]) == kc.MLP_NPARAMS
+        assert len(m["mean"]) == kc.MLP_IN and len(m["std"]) == kc.MLP_IN
+        assert all(v > 0 for v in m["std"])
+        assert np.all(np.isfinite(m["params"]))
+        assert m["validation"]["mse"] < 0.1 * m["validation"]["target_var"]
+    params, norm = scheduler.load_model("cpu", 8)
+    assert params.numel() == kc.MLP_NPARAMS and norm.numel() == 2 * kc.MLP_IN
+
+
+def test_spearman_uses_average_ranks_for_ties():
+    from scipy.stats import spearmanr
+    rng = np.random.default_rng(0)
+    a = rng.integers(0, 5, 300).astype(float)
+    b = a + rng.normal(0, 1, 300)
+    assert abs(scheduler.spearman(a, b) - spearmanr(a, b).statistic) < 1e-12
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
+
+
+def test_generators_are_deterministic_and_follow_the_recipe():
+    w1 = graphgen.workload(5, scale=0.001)
+    w2 = graphgen.workload(5, scale=0.001)
+    (rp, ci), (rp2, ci2) = w1.graphs[0], w2.graphs[0]
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+    assert oracle.validate(rp, ci)
+    # the largest planted clique bounds the degeneracy from below
+    core = oracle.core_numbers(rp, ci)
+    assert core.max() >= max(w1.params["planted"]) - 1
+    w4 = graphgen.workload(4, scale=0.03)
+    assert len(w4.graphs) == len(w4.ks) and all(3 <= k <= 9 for k in w4.ks)
+    for (rp, ci), (n, d, k) in zip(w4.graphs, w4.params["graphs"]):
+        assert len(rp) - 1 == n and oracle.validate(rp, ci)
+        assert abs(len(ci) / n - d) < 0.5 * d  # mean degree near its draw
