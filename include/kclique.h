@@ -24,8 +24,10 @@
  *
  * Ownership: the caller owns every buffer.  The library keeps no pointer after
  * returning and allocates its scratch memory on the device for the duration
- * of a call (stream-ordered), freeing it before returning.  Calls that share a
- * stream are serialised by it; calls on different streams are independent.
+ * of a call (stream-ordered), freeing it before returning; the one exception
+ * is a prepared batch (kclique_plan_*), which holds its device memory until
+ * it is destroyed.  Calls that share a stream are serialised by it; calls on
+ * different streams are independent.
  *
  * Errors: every function returns a kc_status.  On a non-zero status the
  * outputs are unspecified.  No C++ exception crosses this interface.
@@ -131,16 +133,22 @@ int kclique_count(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int
 
 /* Per-vertex participation: per_vertex_out[v] = number of k-cliques that
  * contain v (host array of n entries); count_out (nullable) = total.  The
- * per-vertex values sum to k times the total. */
+ * per-vertex values sum to k times the total.  Each clique found by the
+ * listing (the emit points of Alg. 5 and Alg. 6) or by Pre-List (Alg. 4,
+ * C(n_c - 1, k - 1) per member of a clique component) is credited to each of
+ * its k vertices. */
 int kclique_list_per_vertex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                             uint64_t* per_vertex_out, uint64_t* count_out);
 
-/* Full form of both calls.  per_vertex_out may be NULL (count only).  With
- * opt->device_ptrs the graph and outputs live in device memory. */
+/* Full form of both calls (Sec. 3.1; Alg. 3-6).  per_vertex_out may be NULL
+ * (count only).  With opt->device_ptrs the graph and outputs live in device
+ * memory. */
 int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                      const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out);
 
-/* Many independent graphs in one call: graph g has n[g] vertices, its rows
+/* Many independent graphs in one call (each counted as in Sec. 3.1, all in
+ * one preprocessing pass and one listing launch per bitmap class, as the
+ * disjoint union with a k per vertex): graph g has n[g] vertices, its rows
  * start at row_ptr_cat[row_off[g]] (n[g]+1 entries, local offsets starting at
  * 0) and its columns at col_idx_cat[col_off[g]] (local vertex ids).  k[g] per
  * graph.  counts_out[g] receives graph g's count.  Pointers follow
