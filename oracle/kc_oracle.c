@@ -59,6 +59,13 @@
  *     call included), `isect` counts set intersections (merge joins or
  *     BitJoins), `elems` adds |C| + d+_u per merge join (the cost term of
  *     Lemma 2) and `words` adds ceil(s / 32) per BitJoin.
+ *
+ * Parity status: counts, per-vertex counts, Pre-Core, Pre-List, both
+ * orientations, the coloring and the encoding are pinned by the CPU tests
+ * (brute force, closed forms, core numbers, the paper's worked examples and
+ * encoding table).  The per-root work counters (nodes, isect, elems, words)
+ * are parity unpinned against paper values: the paper prints none; they are
+ * checked only by the Example 4 trace and the Lemma 4 bound.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
