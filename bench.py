@@ -10,7 +10,11 @@ persistent listing kernels.  The learned schedule (MLP trained on per-root
 work logged from the smaller workloads) and the degree schedule run the same
 kernels; both counts must equal each other.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the exact count per second of the learned schedule
+(`value`), both schedules' step times, the roofline of the dominant listing
+launch (algorithmic int32 operations per second against the VALU peak, with
+the HBM bytes the profiler counted for it), and the oracle timed on the host's
+cores as a CPU baseline.
 """
 from __future__ import annotations
 

@@ -13,7 +13,8 @@ SOURCES = ["kc_api.hip", "kc_prep.hip", "kc_sched.hip", "kc_bitcol.hip", "kc_sde
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
-    # packed FP32 instructions stay off (build flags)
+    # packed FP32 instructions stay off: some of their forms have given wrong
+    # results on this hardware, and the kernels here gain nothing from them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
 ]
