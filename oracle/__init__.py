@@ -8,9 +8,10 @@ each function follows and the readings taken where the paper is ambiguous).
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_pins.py`` (closed forms, brute force, the paper's worked
-examples); the per-root work counters have no values printed in the paper and
-are pinned only by hand-derived traces of the paper's SDegree example and by
-consistency invariants ("parity unpinned" against paper values).
+examples).  The per-root work counters have no values printed in the paper;
+they are pinned by hand-derived traces of the paper's own examples (SDegree's
+recursion of Example 4, BitCol's Alg. 6 on the Example 6 / Table 3 local
+graph) and by the Lemma 4 bound.
 """
 from __future__ import annotations
 

@@ -63,9 +63,12 @@
  * Parity status: counts, per-vertex counts, Pre-Core, Pre-List, both
  * orientations, the coloring and the encoding are pinned by the CPU tests
  * (brute force, closed forms, core numbers, the paper's worked examples and
- * encoding table).  The per-root work counters (nodes, isect, elems, words)
- * are parity unpinned against paper values: the paper prints none; they are
- * checked only by the Example 4 trace and the Lemma 4 bound.
+ * encoding table).  The per-root work counters are pinned by hand-derived
+ * traces of the paper's own examples: SDegree's (nodes, isect, elems) by the
+ * Example 4 recursion from v2 and v5, BitCol's (count, nodes, isect, words,
+ * colors, |E_u|) by Alg. 6 run by hand on the Example 6 / Table 3 local graph
+ * at k = 3..6; plus the Lemma 4 bound.  The paper itself prints no per-root
+ * work values, so beyond those traces they rest on the readings above.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>

@@ -376,3 +376,56 @@ def test_bitcol_roots_matches_the_whole_dag_run():
         for key in ("count", "nodes", "isect", "words"):
             assert np.array_equal(sub[key], per[key][roots]), key
         assert total == int(per["count"].sum())
+
+
+def test_paper_bitcol_trace_on_the_encoded_example():
+    """BitColList (Alg. 6) traced by hand on the local graph of Example 6 and
+    Table 3, taken as G_u of one root u.
+
+    DAG: u = 0 points to v1..v6 (ids 1..6) and the 12 edges of the local graph
+    point from the smaller to the larger id, so G_u is exactly that graph and
+    its greedy coloring is Example 6's: colors (v1..v6) = (1, 2, 3, 4, 2, 3),
+    B(v1..v6) = {}, {v1}, {v1,v2}, {v1,v2,v3,v6}, {v1}, {v1,v2,v5} (Table 3).
+
+    k = 4 (top call l = 3, C = all six): v1, v2, v5 fail color >= 3.
+      v3: C' = {v1,v2,v5} (join 1), l = 2: v2 -> |{v1}| = 1 (join 2),
+          v5 -> 1 (join 3)                                    -> 2 cliques
+      v4: C' = {v1,v2,v3,v6} (join 4), l = 2: v2 -> 1 (join 5),
+          v3 -> |{v1,v2}| = 2 (join 6), v6 -> |{v1,v2}| = 2 (join 7) -> 5
+      v6: C' = {v1,v2,v5} (join 8), l = 2: v2 -> 1 (join 9), v5 -> 1 (join 10)
+                                                              -> 2
+      9 cliques (the 9 triangles of the local graph), 10 joins, 4 calls.
+    k = 5 (l = 4): only v4 has color >= 4 (the color prune of Sec. 7.1).
+      v4: C' = {v1,v2,v3,v6} (join 1), l = 3: v3 -> {v1,v2} (join 2),
+          l = 2: v2 -> 1 (join 3); v6 -> {v1,v2} (join 4), l = 2: v2 -> 1
+          (join 5).  2 cliques, 5 joins, 4 calls.
+    k = 3 (l = 2): every vertex of color >= 2 joins once with C:
+      1 + 3 + 4 + 1 + 3 = 12 cliques (the 12 edges), 5 joins, 1 call.
+    k = 6 (l = 5): no vertex has color >= 5: 0 cliques, 0 joins, 1 call.
+    Words: one 32-bit word per join (6 local vertices).  Features of u:
+    4 colors, |E_u| = 12.
+    """
+    exp = G.paper_expected()
+    local = [(1, 2), (1, 3), (1, 4), (1, 5), (1, 6), (2, 3), (2, 4), (2, 6), (3, 4), (3, 5), (4, 6), (5, 6)]
+    n = 7
+    out = {v: [] for v in range(n)}
+    out[0] = [1, 2, 3, 4, 5, 6]
+    for a, b in local:
+        out[a].append(b)
+    drp = np.zeros(n + 1, dtype=np.int32)
+    drp[1:] = np.cumsum([len(out[v]) for v in range(n)])
+    dci = np.asarray([w for v in range(n) for w in sorted(out[v])], dtype=np.int32)
+    # the coloring the trace assumes is the paper's
+    colors, _ = oracle.bitcol_encode(_example_local_graph(), np.arange(1, 7), 3)
+    assert [int(c) for c in colors] == [1, 2, 3, 4, 2, 3]
+    assert int(colors[3]) == int(exp["color_v4"][0])
+    want = {3: (12, 5, 1), 4: (9, 10, 4), 5: (2, 5, 4), 6: (0, 0, 1)}
+    for k, (cnt, joins, calls) in want.items():
+        total, per = oracle.bitcol_dag(drp, dci, k)
+        assert int(per["count"][0]) == cnt, k
+        assert int(per["isect"][0]) == joins, k
+        assert int(per["nodes"][0]) == calls, k
+        assert int(per["words"][0]) == joins, k
+        assert int(per["colors"][0]) == 4 and int(per["edges"][0]) == 12, k
+        sub = oracle.bitcol_roots(drp, dci, k, [0])
+        assert [int(sub[key][0]) for key in ("count", "isect", "nodes", "words")] == [cnt, joins, calls, joins]
