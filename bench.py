@@ -6,24 +6,42 @@ exponent 2.0, max weight sqrt(n * mean degree), with 8 planted cliques
 A step is one whole call of the library on the graph already resident in HBM:
 validation, Pre-Core, Pre-List, degeneracy orientation, staging/coloring/
 encoding, features + MLP inference + binning + task generation, and the
-persistent listing kernels.  The learned schedule (MLP trained on per-root
-work logged from the smaller workloads) and the degree schedule run the same
-kernels; both counts must equal each other.
+persistent listing kernels.  Nothing is skipped or cached between steps.
 
-Prints one JSON line: the exact count per second of the learned schedule
-(`value`), both schedules' step times, the roofline of the dominant listing
-launch (algorithmic int32 operations per second against the VALU peak, with
-the HBM bytes the profiler counted for it), and the oracle timed on the host's
-cores as a CPU baseline.
+Variants, all on the same kernels and launch shape, all required to give the
+same exact count:
+  learned        the learned schedule (MLP work estimates, split by shares of
+                 each word class's estimated work), classes in sequence;
+  degree         the degree schedule (log C(d+, k-1), fixed split counts),
+                 classes in sequence -- the matched comparison;
+  degree_shares  the degree estimate through the learned schedule's split
+                 policy: isolates what the MLP's estimates add;
+  learned_cs2 / degree_cs2   the same two schedules with the word classes'
+                 launches running concurrently.
+
+One step of this workload takes 15-60 s, so the run is bounded by a
+wall-clock budget measured from the start of the process (default 430 s):
+the variants are stepped round-robin (headline first) until each has the
+requested number of steps or the next step would not fit; `steps` reports
+the steps actually timed for the headline variant, and each variant lists its
+own.  Prints one JSON line: the exact count per second of the learned
+schedule (`value`), every variant's step time, the roofline of the dominant
+listing launch (algorithmic int32 operations per second against the VALU
+peak, with the HBM bytes the profiler counted for it), and the oracle timed on
+the host's cores as a CPU baseline.
 """
 from __future__ import annotations
 
-import argparse
-import json
-import math
-import os
-import sys
 import time
+
+T_START = time.monotonic()
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import os  # noqa: E402
+import signal  # noqa: E402
+import statistics  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -33,15 +51,23 @@ MI355X_CUS = 256
 MI355X_CLOCK_HZ = 2.4e9
 # int32 VALU: 4 SIMDs x 16 lanes per CU per clock (v_and_b32, v_bcnt_u32_b32)
 INT32_VALU_PEAK_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_HZ / 1e12
-
+WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32]
 
 # HBM bytes of the dominant listing launch (16-word bitmaps, learned schedule,
-# 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE x
-# 2.000 and WRITE_SIZE x 1.000, factors from a plain 1 GiB copy), valid only
-# for the kernel sources they were taken on.
+# 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE
+# and WRITE_SIZE, each scaled by what the same counter reads for a plain copy
+# of known size), valid only for the kernel sources they were taken on.
 PROFILED_TRAFFIC = {"sources_sha256_16": "18e5b7998d7ebe7e", "word_class": 16,
                     "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.70e9,
                     "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md"}
+
+VARIANTS = {
+    "learned": dict(schedule="learned", class_streams=1),
+    "degree": dict(schedule="degree", class_streams=1),
+    "degree_shares": dict(schedule="degree", class_streams=1, split_policy=2),
+    "learned_cs2": dict(schedule="learned", class_streams=2),
+    "degree_cs2": dict(schedule="degree", class_streams=2),
+}
 
 
 def listing_sources_sha():
@@ -51,6 +77,10 @@ def listing_sources_sha():
         with open(os.path.join(ROOT, "paper_2203_13512_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def elapsed():
+    return time.monotonic() - T_START
 
 
 _CPU_JOB = None
@@ -90,7 +120,7 @@ def cpu_baseline(rp_h, ci_h, k, secs):
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{elapsed():6.1f}s]", *a, file=sys.stderr, flush=True)
 
 
 def copy_calibration(mib: int):
@@ -105,19 +135,53 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
+def roofline_of(st_list, w_name, k, variant):
+    """Roofline of the dominant listing launch: the word class whose
+    persistent kernel ran longest (one launch per class per step; durations
+    from HIP events recorded on the class's own stream), averaged over the
+    timed steps.  Algorithmic work = ceil(s/32) words per BitJoin, AND +
+    popcount = 2 int32 operations per word, against the int32 VALU peak."""
+    ncls = len(WORD_CLASSES)
+    cms = [statistics.fmean(st["class_ms"][c] for st in st_list) for c in range(ncls)]
+    dom = max(range(ncls), key=lambda c: cms[c])
+    W = WORD_CLASSES[dom]
+    st = st_list[-1]
+    dom_s = cms[dom] / 1e3
+    alg_ops = 2.0 * st["class_work"][dom]
+    achieved = alg_ops / dom_s / 1e12 if dom_s > 0 else 0.0
+    pt = PROFILED_TRAFFIC
+    traffic = pt["bytes"] if (pt["sources_sha256_16"] == listing_sources_sha() and pt["word_class"] == W
+                              and pt["workload"] == w_name and pt["k"] == k and variant == "learned") else None
+    list_ms = statistics.fmean(s["list_ms"] for s in st_list)
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT32_VALU_PEAK_TOPS, 3),
+            "unit": "TOP/s", "frac": round(achieved / INT32_VALU_PEAK_TOPS, 5), "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM, profiler counters)",
+            "kernel": f"k_bitcol_list, {W}-word bitmaps", "launch_ms": round(cms[dom], 3),
+            "launches_averaged": len(st_list),
+            "algorithmic_words": int(st["class_work"][dom]), "tasks": int(st["class_tasks"][dom]),
+            "all_classes": {str(WORD_CLASSES[c]): {"ms": round(cms[c], 3), "words": int(st["class_work"][c]),
+                                                   "tasks": int(st["class_tasks"][c])}
+                            for c in range(ncls) if st["class_tasks"][c] > 0},
+            "list_ms": round(list_ms, 3), "bitjoins": int(st["isect"]),
+            "bitjoins_on_reencoded_rows": int(st["isect_compressed"]),
+            # the listing phase as a whole (all classes, in sequence or overlapped)
+            "chip_achieved": round(2.0 * st["work"] / (list_ms / 1e3) / 1e12, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # one k=8 step takes one to two minutes per schedule, so the default run
-    # times one step of each without a warmup step (the code objects are
-    # loaded beforehand by a call on a small graph, outside the timed region)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=2, help="timed steps per variant (bounded by --budget-s)")
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="untimed steps on the full workload before timing (at most 1; the code objects are "
+                         "always loaded first by a call on a small graph)")
+    ap.add_argument("--budget-s", type=float, default=430.0,
+                    help="wall-clock budget of the whole run from process start, in seconds")
     ap.add_argument("--workload", type=int, default=5, help="1, 2, 3 or 5 (see graphgen.workload)")
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--order", default="color")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--schedules", default="learned,degree")
+    ap.add_argument("--variants", default=",".join(VARIANTS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -128,7 +192,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the k-clique path here is a one-GPU "
+                                   "build); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -136,7 +201,7 @@ def main():
 
     import graphgen
     import paper_2203_13512_amd as kc
-    from paper_2203_13512_amd import scheduler
+    from paper_2203_13512_amd import autotune, scheduler
 
     t0 = time.time()
     w = graphgen.workload(args.workload, scale=args.scale)
@@ -151,112 +216,124 @@ def main():
     ci = torch.from_numpy(ci_h).to(dev)
     torch.cuda.synchronize()
 
-    from paper_2203_13512_amd import autotune
-    tuned = autotune.lookup(rp_h, ci_h, k, args.order) if args.order == "color" else {}
-    log(f"autotuned launch shape: {tuned or 'library defaults'}")
-
-    schedules = [s for s in args.schedules.split(",") if s]
-    mlp = None
-    if "learned" in schedules:
-        mlp = scheduler.load_model(dev, k)
-        if mlp is None:
-            log("no trained scheduler model found; running the degree schedule only")
-            schedules = [s for s in schedules if s != "learned"]
+    variants = [v for v in args.variants.split(",") if v]
+    mlp = scheduler.load_model(dev, k)
+    if mlp is None:
+        log("no trained scheduler model found; running the degree schedule only")
+        variants = [v for v in variants if VARIANTS[v]["schedule"] != "learned"]
+    kwargs = {}
+    for v in variants:
+        base = dict(VARIANTS[v])
+        tuned = autotune.lookup(rp_h, ci_h, k, args.order, schedule=base["schedule"]) if args.order == "color" else {}
+        tuned = {key: val for key, val in tuned.items() if key not in base}
+        base.update(tuned)
+        if base["schedule"] == "learned":
+            base["mlp"] = mlp
+        kwargs[v] = base
+        log(f"variant {v}: {({key: val for key, val in base.items() if key != 'mlp'})}")
 
     # load the library's code objects (not a step: a tiny graph, untimed)
     prime = graphgen.erdos_renyi(200, 0.2, seed=1)
-    kc.count(torch.from_numpy(prime[0]).to(dev), torch.from_numpy(prime[1]).to(dev), k, args.order,
-             schedule="degree", **tuned)
+    prp, pci = torch.from_numpy(prime[0]).to(dev), torch.from_numpy(prime[1]).to(dev)
+    for v in variants:
+        kc.count(prp, pci, k, args.order, **kwargs[v])
     torch.cuda.synchronize()
 
-    results = {}
-    for sched in schedules:
-        kw = dict(schedule=sched, stats=True, **tuned)
-        if sched == "learned":
-            kw["mlp"] = mlp
-        for i in range(args.warmup):
-            c, st = kc.count(rp, ci, k, args.order, **kw)
-            torch.cuda.synchronize()
-            log(f"[{sched}] warmup {i}: count={c} total={st['total_ms']:.1f}ms list={st['list_ms']:.1f}ms")
-        times, lists, counts, stats = [], [], [], []
+    head = variants[0]
+    warm = 0
+    if args.warmup > 0:
+        c, st = kc.count(rp, ci, k, args.order, stats=True, **kwargs[head])
         torch.cuda.synchronize()
-        for i in range(args.steps):
+        warm = 1
+        log(f"[{head}] warmup: count={c} total={st['total_ms']:.1f}ms list={st['list_ms']:.1f}ms")
+
+    res = {v: dict(times=[], stats=[], counts=[]) for v in variants}
+    state = {"out": None}
+
+    def build_line():
+        done = {v: r for v, r in res.items() if r["times"]}
+        if head not in done:
+            return None
+        counts = {r["counts"][0] for r in done.values()}
+        R = done[head]
+        step_s = statistics.fmean(R["times"])
+        cnt = R["counts"][0]
+        out = {
+            "metric": "k-cliques/sec on 1 MI355X: learned-scheduled vs degree-scheduled, exact count",
+            "value": cnt / step_s,
+            "unit": "k-cliques/s",
+            "n_gpus": 1,
+            "steps": len(R["times"]),
+            "warmup": warm,
+            "ms_per_step": step_s * 1e3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": f"{w.name} k={k} {args.order} order", "k": k, "order": args.order,
+                       "schedule": head, "n": int(len(rp_h) - 1), "nnz": int(len(ci_h)), "count": cnt,
+                       "counts_agree": len(counts) == 1,
+                       "launch": {key: val for key, val in kwargs[head].items() if key != "mlp"}},
+            "schedules": {v: {"value": r["counts"][0] / statistics.fmean(r["times"]),
+                              "ms_per_step": statistics.fmean(r["times"]) * 1e3,
+                              "median_ms": statistics.median(r["times"]) * 1e3,
+                              "list_ms": statistics.fmean(s["list_ms"] for s in r["stats"]),
+                              "steps": len(r["times"]), "n_tasks": r["stats"][-1]["n_tasks"],
+                              "launch": {key: val for key, val in kwargs[v].items() if key != "mlp"}}
+                          for v, r in done.items()},
+            "roofline": roofline_of(R["stats"], w.name, k, head),
+            "cpu_baseline": cpu,
+            # context only: the paper reports speedups of its methods over its
+            # own CPU baselines (total serial time over its ten datasets), no rates
+            "paper_context": {"sdegree_vs_ddegree": 3.75, "bitcol_vs_ddegcol": 5.67,
+                              "hardware": "4x Intel Xeon 4210R (40 cores, 2.4 GHz), 128 GB RAM; serial runs"},
+            "budget_s": args.budget_s,
+        }
+        sch = out["schedules"]
+        for a, b in [("degree", "learned"), ("degree_cs2", "learned_cs2"), ("degree_shares", "learned")]:
+            if a in sch and b in sch:
+                out[f"speedup_{b}_vs_{a}"] = sch[a]["ms_per_step"] / sch[b]["ms_per_step"]
+        return out
+
+    def emit_and_exit(signum, frame):
+        if state["out"] is not None:
+            print(json.dumps(state["out"]), flush=True)
+        os._exit(0 if state["out"] is not None else 1)
+
+    signal.signal(signal.SIGTERM, emit_and_exit)
+
+    def est(v):
+        t = res[v]["times"]
+        return max(t) if t else (max(max(r["times"]) for r in res.values() if r["times"]) * 3.0
+                                 if any(r["times"] for r in res.values()) else 60.0)
+
+    progress = True
+    while progress:
+        progress = False
+        for v in variants:
+            if len(res[v]["times"]) >= args.steps:
+                continue
+            left = args.budget_s - elapsed()
+            if est(v) * 1.15 + 5.0 > left and res[head]["times"]:
+                log(f"[{v}] next step (~{est(v):.0f}s) does not fit the {left:.0f}s left")
+                continue
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            c, st = kc.count(rp, ci, k, args.order, **kw)
+            c, st = kc.count(rp, ci, k, args.order, stats=True, **kwargs[v])
             torch.cuda.synchronize()
             el = time.perf_counter() - ts
-            times.append(el)
-            lists.append(st["list_ms"])
-            counts.append(c)
-            stats.append(st)
-            log(f"[{sched}] step {i}: count={c} wall={el * 1e3:.1f}ms device={st['total_ms']:.1f}ms "
+            res[v]["times"].append(el)
+            res[v]["stats"].append(st)
+            res[v]["counts"].append(c)
+            progress = True
+            log(f"[{v}] step {len(res[v]['times'])}: count={c} wall={el * 1e3:.1f}ms device={st['total_ms']:.1f}ms "
                 f"prep={st['prep_ms']:.1f} stage={st['stage_ms']:.1f} sched={st['sched_ms']:.1f} "
                 f"list={st['list_ms']:.1f} tasks={st['n_tasks']}")
-        assert len(set(counts)) == 1, counts
-        results[sched] = dict(count=counts[0], step_s=sum(times) / len(times),
-                              list_ms=sum(lists) / len(lists), stats=stats[-1])
-    counts = {s: r["count"] for s, r in results.items()}
-    assert len(set(counts.values())) == 1, f"schedules disagree: {counts}"
-    main_sched = "learned" if "learned" in results else schedules[0]
-    R = results[main_sched]
-    cnt = R["count"]
-    value = cnt / R["step_s"]
-    st = R["stats"]
-    # Roofline of the dominant kernel: the persistent BitCol listing kernel of
-    # the word class with the longest launch (one launch per class per step;
-    # its duration comes from HIP events recorded on the class's own stream).
-    # Algorithmic work = ceil(s/32) words per BitJoin, AND + popcount = 2 int
-    # ops per word, against the int32 VALU peak.
-    cms = list(st["class_ms"])
-    dom = max(range(len(cms)), key=lambda c: cms[c])
-    W = [1, 2, 4, 8, 12, 16, 24, 32][dom]
-    dom_s = cms[dom] / 1e3
-    alg_ops = 2.0 * st["class_work"][dom]
-    achieved = alg_ops / dom_s / 1e12 if dom_s > 0 else 0.0
-    pt = PROFILED_TRAFFIC
-    traffic = pt["bytes"] if (pt["sources_sha256_16"] == listing_sources_sha() and pt["word_class"] == W
-                              and pt["workload"] == w.name and pt["k"] == k and main_sched == "learned") else None
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT32_VALU_PEAK_TOPS, 3),
-                "unit": "TOP/s", "frac": round(achieved / INT32_VALU_PEAK_TOPS, 5), "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM, profiler counters)",
-                "kernel": f"k_bitcol_list, {W}-word bitmaps", "launch_ms": round(cms[dom], 3),
-                "algorithmic_words": int(st["class_work"][dom]), "tasks": int(st["class_tasks"][dom]),
-                "all_classes": {str([1, 2, 4, 8, 12, 16, 24, 32][c]): {
-                    "ms": round(cms[c], 3), "words": int(st["class_work"][c]), "tasks": int(st["class_tasks"][c])}
-                    for c in range(len(cms)) if st["class_tasks"][c] > 0},
-                "list_ms": round(R["list_ms"], 3), "bitjoins": int(st["isect"]),
-                # all classes' launches overlap: the chip-level rate over the listing phase
-                "chip_achieved": round(2.0 * st["work"] / (R["list_ms"] / 1e3) / 1e12, 4)}
-
-
-    out = {
-        "metric": "k-cliques/sec on 1 MI355X: learned-scheduled vs degree-scheduled, exact count",
-        "value": value,
-        "unit": "k-cliques/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": R["step_s"] * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": f"{w.name} k={k} {args.order} order", "k": k, "order": args.order,
-                   "schedule": main_sched, "n": int(len(rp_h) - 1), "nnz": int(len(ci_h)), "count": cnt,
-                   "launch": tuned or "defaults"},
-        "schedules": {s: {"value": r["count"] / r["step_s"], "ms_per_step": r["step_s"] * 1e3,
-                          "list_ms": r["list_ms"], "n_tasks": r["stats"]["n_tasks"]} for s, r in results.items()},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        # context only: the paper reports speedups of its methods over its own
-        # CPU baselines (total serial time over its ten datasets), no rates
-        "paper_context": {"sdegree_vs_ddegree": 3.75, "bitcol_vs_ddegcol": 5.67,
-                          "hardware": "4x Intel Xeon 4210R (40 cores, 2.4 GHz), 128 GB RAM; serial runs"},
-    }
-    if "learned" in results and "degree" in results:
-        out["learned_speedup_vs_degree"] = results["degree"]["step_s"] / results["learned"]["step_s"]
+            state["out"] = build_line()
+    out = build_line()
+    allc = {c for r in res.values() for c in r["counts"]}
+    assert len(allc) == 1, f"variants disagree: {allc}"
     print(json.dumps(out), flush=True)
 
 

@@ -23,11 +23,13 @@
  * (The paper treats k >= 3; the two linear cases follow Sec. 8.)
  *
  * Ownership: the caller owns every buffer.  The library keeps no pointer after
- * returning and allocates its scratch memory on the device for the duration
- * of a call (stream-ordered), freeing it before returning; the one exception
- * is a prepared batch (kclique_plan_*), which holds its device memory until
- * it is destroyed.  Calls that share a stream are serialised by it; calls on
- * different streams are independent.
+ * returning.  Its device scratch memory comes either from a caller-owned
+ * workspace (kc_options.workspace, sized by kclique_workspace_size) or, when
+ * none is given, from stream-ordered allocations freed before the call
+ * returns; the one exception is a prepared batch (kclique_plan_*), which holds
+ * its device memory until it is destroyed.  Calls that share a stream are
+ * serialised by it; calls on different streams are independent (they must not
+ * share a workspace).
  *
  * Errors: every function returns a kc_status.  On a non-zero status the
  * outputs are unspecified.  No C++ exception crosses this interface.
@@ -48,7 +50,8 @@ typedef enum {
   KC_ENOMEM = -2,        /* device allocation failed */
   KC_EOVERFLOW = -3,     /* a count does not fit in 64 bits (e.g. C(201,20)) */
   KC_EDEVICE = -4,       /* a HIP runtime call failed or no device */
-  KC_EUNSUPPORTED = -5   /* a local subgraph exceeds the supported size */
+  KC_EUNSUPPORTED = -5,  /* a local subgraph exceeds the supported size */
+  KC_EWORKSPACE = -6     /* the caller's workspace is smaller than the call needs */
 } kc_status;
 
 /* Orientation / algorithm. */
@@ -110,6 +113,13 @@ typedef struct {
   int32_t class_streams;  /* BitCol: listing kernels of the word classes 1 = one after another on `stream`,
                              2 = concurrently on streams of their own, 0 = auto (1 for the learned
                              schedule, 2 for the degree schedule) */
+  int32_t split_policy;   /* BitCol: which roots are split into depth-1 / depth-2 work items, given each
+                             root's work estimate (the schedule's key).  0 = the schedule's own (2 for
+                             LEARNED, 1 for DEGREE); 1 = fixed counts: per word class the slots/4
+                             roots of highest key split twice, the next 4 x slots once (slots = 4 per
+                             CU); 2 = shares: a root whose estimate exceeds 1/(8 slots) of its class's
+                             estimated total splits once, 64 such shares twice.  DEGREE with policy 2
+                             isolates what the MLP's estimates add over log C(d+, k-1). */
   /* optional per-vertex logs, device pointers of n entries (NULL = off):
    * the root's listing work (as kc_stats.work) and its features */
   uint64_t* root_work;
@@ -120,6 +130,11 @@ typedef struct {
   const int32_t* vertex_k;/* device pointer, n entries, or NULL: a k per vertex (constant on every
                              connected component; the k argument must be their maximum).  Used to count
                              many graphs with different k in one call. */
+  void* workspace;         /* device memory owned by the caller, or NULL: the call takes all its scratch
+                             memory from it (no device allocation by the library); its contents on
+                             entry are irrelevant and on return unspecified.  At least the size
+                             kclique_workspace_size reports for the same arguments and options. */
+  size_t workspace_bytes;
   kc_stats* stats;        /* host pointer or NULL */
 } kc_options;
 
@@ -145,6 +160,20 @@ int kclique_list_per_vertex(int32_t n, const int32_t* row_ptr, const int32_t* co
  * memory. */
 int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                      const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out);
+
+/* Scratch memory a kclique_count_ex call with the same arguments and options
+ * needs when it takes it from kc_options.workspace; per_vertex = 1 when that
+ * call passes per_vertex_out.  The workspace fields and the per-root log
+ * pointers of `opt` are ignored here (nothing of the caller's is written).
+ * The amount depends on the graph itself -- the staged bitmaps of Sec. 7.3
+ * and the work items follow the out-degrees of the oriented graph after
+ * Pre-Core and Pre-List -- so the query runs the call's preparation
+ * (validation, Sec. 5 preprocessing, orientation, staging, scheduling) on the
+ * device, with scratch it allocates and frees itself, and stops before the
+ * listing.  *bytes receives the size (a multiple of 256).  Errors as for
+ * kclique_count_ex (a malformed graph gives KC_EINVAL here already). */
+int kclique_workspace_size(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                           int32_t per_vertex, const kc_options* opt, size_t* bytes);
 
 /* Many independent graphs in one call (each counted as in Sec. 3.1, all in
  * one preprocessing pass and one listing launch per bitmap class, as the
@@ -200,9 +229,17 @@ int kc_mlp_forward(const float* params, const float* x, int32_t rows, float* y, 
  * target; grad (KC_MLP_NPARAMS) receives d loss / d params, loss_out (one
  * float, device) the loss.  Then, if lr > 0, one Adam step (Kingma and Ba)
  * with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 updates params in place using
- * the moment buffers m, v (KC_MLP_NPARAMS each) and the 1-based step t. */
+ * the moment buffers m, v (KC_MLP_NPARAMS each) and the 1-based step t.
+ * workspace: device scratch of at least kc_mlp_workspace_size(rows) bytes
+ * owned by the caller, or NULL (the library allocates and frees it).
+ * Gradients are summed in a fixed order: identical inputs give identical
+ * bits. */
 int kc_mlp_train_step(float* params, const float* x, const float* target, int32_t rows, float* grad, float* loss_out,
-                      float* m, float* v, int32_t t, float lr, void* stream);
+                      float* m, float* v, int32_t t, float lr, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* Scratch bytes kc_mlp_train_step needs for a minibatch of `rows` rows. */
+int kc_mlp_workspace_size(int32_t rows, size_t* bytes);
 
 const char* kc_status_string(int status);
 

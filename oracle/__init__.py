@@ -68,6 +68,7 @@ def _load():
         "orc_bitcol_encode": [i32, vp, vp, i32, vp, vp],
         "orc_bitcol_dag": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp],
         "orc_bitcol_roots": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp],
+        "orc_sdegree_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
         "orc_method_count": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     }
@@ -225,6 +226,19 @@ def sdegree_dag(drp, dci, k: int):
     arrs = [np.zeros(max(n, 1), dtype=np.uint64) for _ in range(4)]
     _check(_load().orc_sdegree_dag(n, _p(drp), _p(dci), k, _p(c), *[_p(a) for a in arrs]), "sdegree_dag")
     return int(c[0]), dict(zip(["count", "nodes", "isect", "elems"], [a[:n] for a in arrs]))
+
+
+def sdegree_roots(drp, dci, k: int, roots):
+    """SDegree from the listed roots of the DAG only; dict of per-root arrays
+    (count, nodes, isect, elems) in the order of `roots`."""
+    drp, dci = _csr(drp, dci)
+    n = len(drp) - 1
+    roots = np.ascontiguousarray(roots, dtype=np.int32)
+    r = max(len(roots), 1)
+    u = [np.zeros(r, dtype=np.uint64) for _ in range(4)]
+    _check(_load().orc_sdegree_roots(n, _p(drp), _p(dci), k, len(roots), _p(roots), *[_p(a) for a in u]),
+           "sdegree_roots")
+    return dict(zip(["count", "nodes", "isect", "elems"], [a[:len(roots)] for a in u]))
 
 
 def greedy_color(adj: np.ndarray, ids):

@@ -31,7 +31,8 @@
  *   orc_degree_dag       degree ordering of Sec. 6.2: u -> v iff
  *                        (d_u, u) < (d_v, v) on the reduced graph.
  *   orc_degeneracy_dag   degeneracy ordering (Sec. 7.4) as a synchronous peel.
- *   orc_sdegree_dag      SDegree, Alg. 5, instrumented per root.
+ *   orc_sdegree_dag      SDegree, Alg. 5, instrumented per root (orc_sdegree_roots:
+ *                        the same from a list of roots).
  *   orc_greedy_color     greedy coloring in inverse degree order (Sec. 7.1).
  *   orc_bitcol_dag       BitCol, Alg. 6, instrumented per root.
  *
@@ -576,6 +577,41 @@ int orc_sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t 
   if (S.status) return S.status;
   *count = S.count;
   return ORC_OK;
+}
+
+/* The same for a list of roots only (sampled or sliced runs on large graphs):
+ * entry i of each output describes roots[i]. */
+int orc_sdegree_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t nroots,
+                      const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                      uint64_t* root_elems) {
+  if (n < 0 || k < 3 || nroots < 0) return ORC_EINVAL;
+  for (int32_t i = 0; i < nroots; ++i)
+    if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
+  int32_t md = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (drp[u + 1] - drp[u] > md) md = drp[u + 1] - drp[u];
+  sdeg_t S;
+  memset(&S, 0, sizeof(S));
+  S.drp = drp;
+  S.dcol = dcol;
+  S.stride = md + 1;
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
+  if (!S.buf) return ORC_ENOMEM;
+  for (int32_t i = 0; i < nroots && !S.status; ++i) {
+    int32_t u = roots[i];
+    int32_t du = drp[u + 1] - drp[u];
+    uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, e0 = S.elems;
+    if (du >= k - 1) {
+      memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
+      sdegree_list(&S, k - 1, S.buf, du, 0);
+    }
+    root_count[i] = S.count - c0;
+    if (root_nodes) root_nodes[i] = S.nodes - n0;
+    if (root_isect) root_isect[i] = S.isect - i0;
+    if (root_elems) root_elems[i] = S.elems - e0;
+  }
+  free(S.buf);
+  return S.status;
 }
 
 /* ----------------------------------------------------- greedy coloring */

@@ -73,6 +73,48 @@ def loss_and_grad(p, x, t):
     return float(np.mean(err ** 2)), pack(g)
 
 
+def grad_magnitude(p, x, t):
+    """The magnitude each gradient entry is computed from: the chain rule of
+    loss_and_grad with every weight, input, target and intermediate replaced
+    by its absolute value (ReLU masks kept).  Rounding in any order of the
+    same products and sums moves an entry by at most a small multiple of
+    (number of rounded operations) x unit roundoff x this magnitude, the
+    classical forward error bound for sums and dot products."""
+    P = unpack(p)
+    x = np.asarray(x, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    B = x.shape[0]
+    z1 = x @ P["W1"].T + P["b1"]
+    m1 = z1 > 0
+    z2 = np.maximum(z1, 0.0) @ P["W2"].T + P["b2"]
+    m2 = z2 > 0
+    a1 = (np.abs(x) @ np.abs(P["W1"]).T + np.abs(P["b1"])) * m1
+    a2 = (a1 @ np.abs(P["W2"]).T + np.abs(P["b2"])) * m2
+    ya = a2 @ np.abs(P["W3"]) + abs(P["b3"][0])
+    dya = 2.0 * (ya + np.abs(t)) / B
+    dz2a = np.outer(dya, np.abs(P["W3"])) * m2
+    dz1a = (dz2a @ np.abs(P["W2"])) * m1
+    g = {"W3": dya @ a2, "b3": np.array([dya.sum()]), "W2": dz2a.T @ a1, "b2": dz2a.sum(axis=0),
+         "W1": dz1a.T @ np.abs(x), "b1": dz1a.sum(axis=0)}
+    return pack(g)
+
+
+def relu_margin(p, x):
+    """Per row: the smallest |pre-activation| of either hidden layer relative
+    to the magnitude of its terms.  Rows with a tiny margin may have a ReLU
+    mask that rounding can flip."""
+    P = unpack(p)
+    x = np.asarray(x, dtype=np.float64)
+    z1 = x @ P["W1"].T + P["b1"]
+    a1 = np.abs(x) @ np.abs(P["W1"]).T + np.abs(P["b1"])
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ P["W2"].T + P["b2"]
+    a2 = h1 @ np.abs(P["W2"]).T + np.abs(P["b2"])
+    r1 = np.abs(z1) / np.maximum(a1, 1e-300)
+    r2 = np.abs(z2) / np.maximum(a2, 1e-300)
+    return np.minimum(r1.min(axis=1), r2.min(axis=1))
+
+
 def adam_step(p, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     m = b1 * m + (1 - b1) * grad
     v = b2 * v + (1 - b2) * grad * grad

@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkclique.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "kclique.h")
 
-OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
 ORDERS = {"degree": 0, "color": 1}
 SCHEDULES = {"degree": 0, "learned": 1}
 MLP_IN, MLP_HIDDEN = 4, 64
@@ -61,9 +61,10 @@ class Options(ctypes.Structure):
         ("schedule", ctypes.c_int32), ("mlp_params", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p),
         ("waves_per_root", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
         ("split_threshold", ctypes.c_float), ("compress", ctypes.c_int32), ("compress_level", ctypes.c_int32),
-        ("class_streams", ctypes.c_int32),
+        ("class_streams", ctypes.c_int32), ("split_policy", ctypes.c_int32),
         ("root_work", ctypes.c_void_p), ("root_isect", ctypes.c_void_p),
         ("root_features", ctypes.c_void_p), ("root_count", ctypes.c_void_p), ("vertex_k", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stats", ctypes.POINTER(Stats)),
     ]
 
@@ -100,7 +101,12 @@ def _lib():
     L.kc_mlp_forward.restype = ctypes.c_int
     L.kc_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
     L.kc_mlp_train_step.restype = ctypes.c_int
-    L.kc_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.kc_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, ctypes.c_size_t, vp]
+    L.kc_mlp_workspace_size.restype = ctypes.c_int
+    L.kc_mlp_workspace_size.argtypes = [i32, ctypes.POINTER(ctypes.c_size_t)]
+    L.kclique_workspace_size.restype = ctypes.c_int
+    L.kclique_workspace_size.argtypes = [i32, vp, vp, i32, i32, i32, ctypes.POINTER(Options),
+                                         ctypes.POINTER(ctypes.c_size_t)]
     L.kc_options_init.restype = None
     L.kc_options_init.argtypes = [ctypes.POINTER(Options)]
     _LIB = L
@@ -128,10 +134,68 @@ def _check(st: int, what: str):
         raise KCliqueError(st, what)
 
 
+_OPTION_KEYS = ("waves_per_root", "chunk", "split", "split_threshold", "compress", "compress_level",
+                "class_streams", "split_policy")
+
+
+def _options(schedule="degree", mlp=None, trusted=False, **launch):
+    """kc_options for the keyword arguments of count(); returns (opt, keep)."""
+    L = _lib()
+    opt = Options()
+    L.kc_options_init(ctypes.byref(opt))
+    opt.trusted_input = 1 if trusted else 0
+    opt.schedule = SCHEDULES[schedule]
+    for key, v in launch.items():
+        if key not in _OPTION_KEYS:
+            raise TypeError(f"unknown option {key!r}")
+        setattr(opt, key, v)
+    keep = []
+    if schedule == "learned":
+        if mlp is None:
+            raise ValueError("the learned schedule needs mlp=(params, norm) device tensors")
+        params, norm = mlp
+        opt.mlp_params = params.data_ptr()
+        opt.mlp_norm = norm.data_ptr()
+        keep += [params, norm]
+    return opt, keep
+
+
+def _device_csr(row_ptr, col_idx):
+    import torch
+    rp = row_ptr.contiguous()
+    ci = col_idx.contiguous()
+    if rp.dtype != torch.int32 or ci.dtype != torch.int32:
+        raise TypeError("row_ptr and col_idx must be int32")
+    return rp, ci
+
+
+def workspace_size(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False,
+                   schedule: str = "degree", mlp=None, trusted: bool = False, **launch) -> int:
+    """Bytes of device scratch a count() with the same arguments takes from a
+    caller-owned workspace (``kclique_workspace_size``: runs the call's
+    preparation on the device and stops before the listing)."""
+    opt, keep = _options(schedule, mlp, trusted, **launch)
+    out = ctypes.c_size_t(0)
+    if _is_torch(row_ptr) and row_ptr.is_cuda:
+        rp, ci = _device_csr(row_ptr, col_idx)
+        opt.device_ptrs = 1
+        opt.stream = _torch_stream(rp.device)
+        rc = _lib().kclique_workspace_size(rp.numel() - 1, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k,
+                                           ORDERS[order], 1 if per_vertex else 0, ctypes.byref(opt),
+                                           ctypes.byref(out))
+    else:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        rc = _lib().kclique_workspace_size(len(rp) - 1, rp.ctypes.data, ci.ctypes.data if ci.size else None, k,
+                                           ORDERS[order], 1 if per_vertex else 0, ctypes.byref(opt),
+                                           ctypes.byref(out))
+    _check(rc, "kclique_workspace_size")
+    return int(out.value)
+
+
 def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False, schedule: str = "degree",
-          mlp=None, trusted: bool = False, waves_per_root: int = 0, chunk: int = 0, split: int = 0,
-          split_threshold: float = 0.0, compress: int = 0, compress_level: int = 0, class_streams: int = 0,
-          root_logs: bool = False, stats: bool = False):
+          mlp=None, trusted: bool = False, root_logs: bool = False, stats: bool = False, workspace=None,
+          **launch):
     """Number of k-cliques (and per-vertex participation).
 
     Returns ``count`` or, with ``per_vertex``, ``(count, pv)`` where pv[v]
@@ -139,31 +203,34 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
     GPU for GPU input, numpy array otherwise).  With ``stats`` a dict of the
     call's timings and work counters is appended; with ``root_logs`` (GPU
     input only) the per-vertex root logs (work, joins, features, cliques
-    attributed to the vertex) are added to that dict.
+    attributed to the vertex) are added to that dict.  ``workspace``: None
+    (the library allocates its scratch), a CUDA uint8 tensor owned by the
+    caller (at least workspace_size() bytes), or "torch" (sized with
+    workspace_size() and allocated by torch for this call).  ``launch``:
+    waves_per_root, chunk, split, split_threshold, compress, compress_level,
+    class_streams, split_policy (kc_options; none changes a result).
     """
     L = _lib()
-    opt = Options()
-    L.kc_options_init(ctypes.byref(opt))
+    opt, keep = _options(schedule, mlp, trusted, **launch)
     st = Stats()
     opt.stats = ctypes.pointer(st)
-    opt.trusted_input = 1 if trusted else 0
-    opt.schedule = SCHEDULES[schedule]
-    opt.waves_per_root = waves_per_root
-    opt.chunk = chunk
-    opt.split = split
-    opt.split_threshold = split_threshold
-    opt.compress = compress
-    opt.compress_level = compress_level
-    opt.class_streams = class_streams
     out = ctypes.c_uint64(0)
-    keep = []
     on_gpu = _is_torch(row_ptr) and row_ptr.is_cuda
+    if isinstance(workspace, str):
+        if workspace != "torch":
+            raise ValueError("workspace must be None, a device tensor or 'torch'")
+        import torch
+        nbytes = workspace_size(row_ptr, col_idx, k, order, per_vertex=per_vertex, schedule=schedule, mlp=mlp,
+                                trusted=trusted, **launch)
+        dev = row_ptr.device if on_gpu else torch.device("cuda")
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+        keep.append(workspace)
     if on_gpu:
         import torch
-        rp = row_ptr.contiguous()
-        ci = col_idx.contiguous()
-        if rp.dtype != torch.int32 or ci.dtype != torch.int32:
-            raise TypeError("row_ptr and col_idx must be int32")
+        rp, ci = _device_csr(row_ptr, col_idx)
         n = rp.numel() - 1
         dev = rp.device
         opt.device_ptrs = 1
@@ -179,13 +246,6 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
             opt.root_isect = logs["isect"].data_ptr()
             opt.root_features = logs["features"].data_ptr()
             opt.root_count = logs["count"].data_ptr()
-        if schedule == "learned":
-            if mlp is None:
-                raise ValueError("the learned schedule needs mlp=(params, norm) device tensors")
-            params, norm = mlp
-            opt.mlp_params = params.data_ptr()
-            opt.mlp_norm = norm.data_ptr()
-            keep += [params, norm]
         rc = L.kclique_count_ex(n, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k, ORDERS[order],
                                 ctypes.byref(opt), ctypes.byref(out), pv.data_ptr() if pv is not None else None)
         _check(rc, "kclique_count_ex")
@@ -329,15 +389,24 @@ def mlp_forward(params, x):
     return y
 
 
-def mlp_train_step(params, x, target, m=None, v=None, t: int = 1, lr: float = 0.0):
+def mlp_train_step(params, x, target, m=None, v=None, t: int = 1, lr: float = 0.0, workspace=None):
     """One minibatch step; returns (loss tensor[1], grad tensor).  With lr > 0
-    the parameters are updated in place by Adam using moments m, v."""
+    the parameters are updated in place by Adam using moments m, v.
+    ``workspace``: None (the library allocates) or a CUDA uint8 tensor of at
+    least mlp_workspace_size(rows) bytes."""
     import torch
     rows = x.shape[0]
     grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    ws, wsb = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None else (None, 0)
     _check(_lib().kc_mlp_train_step(params.data_ptr(), x.contiguous().data_ptr(), target.contiguous().data_ptr(),
                                     rows, grad.data_ptr(), loss.data_ptr(),
                                     m.data_ptr() if m is not None else None, v.data_ptr() if v is not None else None,
-                                    t, lr, _torch_stream(x.device)), "kc_mlp_train_step")
+                                    t, lr, ws, wsb, _torch_stream(x.device)), "kc_mlp_train_step")
     return loss, grad
+
+
+def mlp_workspace_size(rows: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib().kc_mlp_workspace_size(rows, ctypes.byref(out)), "kc_mlp_workspace_size")
+    return int(out.value)

@@ -58,10 +58,19 @@ def load_cache(path: str = CACHE) -> dict:
         return json.load(f)
 
 
-def lookup(row_ptr, col_idx, k: int, order: str = "color", path: str = CACHE) -> dict:
-    """Tuned kc.count keyword arguments for this graph and k ({} if untuned)."""
-    e = load_cache(path).get(signature(row_ptr, col_idx, k, order))
-    return dict(e["best"]) if e else {}
+def lookup(row_ptr, col_idx, k: int, order: str = "color", path: str = CACHE, schedule: str | None = None) -> dict:
+    """Tuned kc.count keyword arguments for this graph and k ({} if untuned).
+    With `schedule`, the shape tuned under that schedule if there is one, else
+    the shape tuned under the other schedule (same kernels, same tuning)."""
+    sig = signature(row_ptr, col_idx, k, order)
+    cache = load_cache(path)
+    keys = ([f"{sig}/{schedule}"] if schedule else []) + [sig]
+    keys += [key for key in cache if key.startswith(sig + "/")]
+    for key in keys:
+        e = cache.get(key)
+        if e:
+            return dict(e["best"])
+    return {}
 
 
 def tune(row_ptr, col_idx, k: int, order: str = "color", space=SPACE, log=print, proxy: bool = False, **count_kw):
@@ -89,11 +98,14 @@ def main(argv=None):
     import graphgen
     argv = argv if argv is not None else sys.argv[1:]
     from paper_2203_13512_amd import scheduler
-    jobs = [tuple(int(x) for x in a.split(":")) for a in argv] or [(5, 8), (5, 7), (2, 7)]
+    # jobs "workload:k" (learned schedule when a model exists) or "workload:k:degree"
+    jobs = [tuple(a.split(":")) for a in argv] or [("5", "8"), ("5", "7"), ("2", "7")]
     cache = load_cache()
     dev = torch.device("cuda:0")
-    for cfg, k in jobs:
-        mlp = scheduler.load_model(dev, k)
+    for job in jobs:
+        cfg, k = int(job[0]), int(job[1])
+        sched = job[2] if len(job) > 2 else "learned"
+        mlp = scheduler.load_model(dev, k) if sched == "learned" else None
         kw = dict(schedule="learned", mlp=mlp) if mlp is not None else {}
         w = graphgen.workload(cfg)
         rp_h, ci_h = w.graphs[0]
@@ -102,8 +114,10 @@ def main(argv=None):
         t = time.time()
         print(f"{w.name} k={k}", flush=True)
         best, info = tune(rp, ci, k, "color", **kw)
-        cache[signature(rp_h, ci_h, k, "color")] = dict(workload=w.name, k=k, order="color",
-                                                        schedule=kw.get("schedule", "degree"), best=best, **info)
+        sig = signature(rp_h, ci_h, k, "color")
+        used = kw.get("schedule", "degree")
+        cache[sig if used == "learned" else f"{sig}/{used}"] = dict(workload=w.name, k=k, order="color",
+                                                                   schedule=used, best=best, **info)
         print(f"  best {best} ({time.time() - t:.1f}s)", flush=True)
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1)

@@ -26,6 +26,7 @@ extern "C" const char* kc_status_string(int status) {
     case KC_EOVERFLOW: return "count does not fit in 64 bits";
     case KC_EDEVICE: return "HIP runtime error";
     case KC_EUNSUPPORTED: return "local subgraph larger than supported";
+    case KC_EWORKSPACE: return "workspace smaller than the call needs (see kclique_workspace_size)";
   }
   return "unknown status";
 }
@@ -51,8 +52,20 @@ __global__ void k_small_k(int32_t n, const int32_t* __restrict__ rp, int32_t k, 
   pv[v] = k == 1 ? 1ull : (unsigned long long)(rp[v + 1] - rp[v]);
 }
 
+// Timing events of a call, created only when statistics are asked for.
 struct HostEvents {
   hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  int init(bool want) {
+    on = want;
+    if (on)
+      for (auto& x : e) KC_HIP(hipEventCreate(&x));
+    return KC_OK;
+  }
+  int record(int i, hipStream_t s) {
+    if (on) KC_HIP(hipEventRecord(e[i], s));
+    return KC_OK;
+  }
   ~HostEvents() {
     for (auto& x : e)
       if (x) (void)hipEventDestroy(x);
@@ -61,10 +74,13 @@ struct HostEvents {
 
 // With `cap` the call is prepared only: everything up to the listing phase
 // runs (in `ext_scr`, which the caller keeps), and the listing phase is handed
-// over in `cap` instead of being launched (BitCol counting only).
+// over in `cap` instead of being launched (BitCol counting only).  With
+// `size_out` the call runs up to the listing phase on scratch it allocates
+// itself and reports the workspace an identical call needs.
 static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                       const kc_options* opt_in, uint64_t* count_out, uint64_t* pv_out,
-                      kc_scratch* ext_scr = nullptr, kc_capture* cap = nullptr) {
+                      kc_scratch* ext_scr = nullptr, kc_capture* cap = nullptr, size_t* size_out = nullptr,
+                      bool size_pv = false) {
   kc_options defaults;
   memset(&defaults, 0, sizeof(defaults));
   const kc_options* opt = opt_in ? opt_in : &defaults;
@@ -73,16 +89,18 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   if (order != KC_ORDER_DEGREE && order != KC_ORDER_COLOR) return KC_EINVAL;
   if (opt->schedule != KC_SCHED_DEGREE && opt->schedule != KC_SCHED_LEARNED) return KC_EINVAL;
   if (n > 0 && !row_ptr) return KC_EINVAL;
+  if (opt->workspace && !ext_scr && !size_out && opt->workspace_bytes == 0) return KC_EWORKSPACE;
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return KC_EDEVICE;
   hipStream_t s = (hipStream_t)opt->stream;
   kc_stats* stats = opt->stats;
   if (stats) memset(stats, 0, sizeof(*stats));
   HostEvents ev;
-  for (auto& x : ev.e) KC_HIP(hipEventCreate(&x));
-  KC_HIP(hipEventRecord(ev.e[0], s));
+  KC_TRY(ev.init(stats != nullptr && !size_out));
+  KC_TRY(ev.record(0, s));
 
-  kc_scratch local_scr(s);
+  const bool own_arena = opt->workspace && !ext_scr && !size_out;
+  kc_scratch local_scr(s, own_arena ? opt->workspace : nullptr, own_arena ? opt->workspace_bytes : 0);
   kc_scratch& scr = ext_scr ? *ext_scr : local_scr;
   // ---- graph on the device
   kc_dev_graph g;
@@ -123,8 +141,10 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   KC_HIP(hipMemsetAsync(prelist_d, 0, sizeof(unsigned long long) * 2, s));
   KC_HIP(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * 8, s));
   unsigned long long* pv_d = nullptr;
-  if (pv_out) {
-    if (opt->device_ptrs) pv_d = (unsigned long long*)pv_out;
+  kc_scratch pv_standin(s);  // a size query's stand-in for the caller's device array (not counted)
+  if (pv_out || size_pv) {
+    if (opt->device_ptrs && pv_out) pv_d = (unsigned long long*)pv_out;
+    else if (opt->device_ptrs) KC_TRY(pv_standin.get(&pv_d, (size_t)n + 1));
     else KC_TRY(scr.get(&pv_d, (size_t)n + 1));
     if (n > 0) KC_HIP(hipMemsetAsync(pv_d, 0, sizeof(unsigned long long) * (size_t)n, s));
   }
@@ -157,14 +177,14 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
       k_small_k<<<(n + 255) / 256, 256, 0, s>>>(n, g.rp, k, pv_d);
       KC_HIP(hipGetLastError());
     }
-    KC_HIP(hipEventRecord(ev.e[1], s));
-    KC_HIP(hipEventRecord(ev.e[2], s));
+    KC_TRY(ev.record(1, s));
+    KC_TRY(ev.record(2, s));
   } else {
     if (k > KC_KMAX_LIMIT) return KC_EUNSUPPORTED;
     kc_prep_out prep;
     KC_TRY(kc_preprocess(g, k, vk, order, prelist_d, pv_d, (unsigned long long*)opt->root_count, flags, &prep,
                          scr, s));
-    KC_HIP(hipEventRecord(ev.e[1], s));
+    KC_TRY(ev.record(1, s));
     int32_t *roots, *rinfo;
     KC_TRY(scr.get(&roots, (size_t)n + 1));
     KC_TRY(scr.get(&rinfo, 4));
@@ -195,9 +215,15 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     c.opt = opt;
     c.stats = stats;
     c.capture = cap;
-    KC_HIP(hipEventRecord(ev.e[2], s));
+    c.size_only = size_out != nullptr;
+    KC_TRY(ev.record(2, s));
     if (order == KC_ORDER_DEGREE) KC_TRY(kc_list_sdegree(c, scr, s));
     else KC_TRY(kc_list_bitcol(c, scr, s));
+    if (size_out) {
+      KC_HIP(hipStreamSynchronize(s));
+      *size_out = scr.need;
+      return KC_OK;
+    }
     if (cap) {
       KC_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
       KC_HIP(hipStreamSynchronize(s));
@@ -213,7 +239,11 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
       stats->max_core = prep.max_core;
     }
   }
-  KC_HIP(hipEventRecord(ev.e[3], s));
+  if (size_out) {  // k <= 2 or k > n: nothing to list
+    *size_out = scr.need;
+    return KC_OK;
+  }
+  KC_TRY(ev.record(3, s));
   // ---- results
   unsigned long long hres[2] = {0, 0}, hcnt[8];
   KC_HIP(hipMemcpyAsync(hres, count_d, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -232,8 +262,8 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   *count_out = total;
   if (stats) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, ev.e[0], ev.e[3]) == hipSuccess) stats->total_ms = t;
-    if (hipEventElapsedTime(&t, ev.e[0], ev.e[1]) == hipSuccess) stats->prep_ms = t;
+    if (ev.on && hipEventElapsedTime(&t, ev.e[0], ev.e[3]) == hipSuccess) stats->total_ms = t;
+    if (ev.on && hipEventElapsedTime(&t, ev.e[0], ev.e[1]) == hipSuccess) stats->prep_ms = t;
     stats->prelist_count = hres[1];
     stats->nodes = hcnt[0];
     stats->isect = hcnt[1];
@@ -248,6 +278,24 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
 extern "C" int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                                 const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out) {
   return count_impl(n, row_ptr, col_idx, k, order, opt, count_out, per_vertex_out);
+}
+
+extern "C" int kclique_workspace_size(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k,
+                                      int32_t order, int32_t per_vertex, const kc_options* opt, size_t* bytes) {
+  if (!bytes) return KC_EINVAL;
+  *bytes = 0;
+  kc_options o;
+  if (opt) o = *opt;
+  else memset(&o, 0, sizeof(o));
+  o.workspace = nullptr;
+  o.workspace_bytes = 0;
+  o.stats = nullptr;
+  o.root_work = nullptr;
+  o.root_isect = nullptr;
+  o.root_features = nullptr;
+  o.root_count = nullptr;
+  uint64_t unused = 0;
+  return count_impl(n, row_ptr, col_idx, k, order, &o, &unused, nullptr, nullptr, nullptr, bytes, per_vertex != 0);
 }
 
 extern "C" int kclique_count(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
@@ -393,6 +441,8 @@ static int build_union(int32_t num_graphs, const int32_t* n, const int64_t* row_
 static kc_options union_options(const kc_options& o, const BatchUnion& U, unsigned long long* rc) {
   kc_options u = o;
   u.device_ptrs = 1;
+  u.workspace = nullptr;  // batched calls and plans allocate their own scratch
+  u.workspace_bytes = 0;
   u.vertex_k = U.vk;
   u.root_count = (uint64_t*)rc;
   u.root_work = nullptr;

@@ -1623,19 +1623,30 @@ static int bitcol_replay_launch(const void* state, hipStream_t st) {
 
 static void bitcol_replay_destroy(void* state) { delete (BitcolReplay*)state; }
 
+// A pair of timing events, created only when statistics are asked for.
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
   ~EventPair() {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
   }
-  int init() {
+  int init(bool on) {
+    if (!on) return KC_OK;
     KC_HIP(hipEventCreate(&a));
     KC_HIP(hipEventCreate(&b));
     return KC_OK;
   }
+  int start(hipStream_t s) {
+    if (a) KC_HIP(hipEventRecord(a, s));
+    return KC_OK;
+  }
+  int stop(hipStream_t s) {
+    if (b) KC_HIP(hipEventRecord(b, s));
+    return KC_OK;
+  }
   float ms() {
     float t = 0.f;
+    if (!a || !b) return 0.f;
     if (hipEventSynchronize(b) != hipSuccess) return 0.f;
     if (hipEventElapsedTime(&t, a, b) != hipSuccess) return 0.f;
     return t;
@@ -1648,11 +1659,12 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   const bool pv = c.pv != nullptr;
   const kc_options* opt = c.opt;
   const int max_class = pv ? 5 : 7;
+  const bool timed = c.stats != nullptr && !c.size_only;
   EventPair ev_stage, ev_sched, ev_list;
-  KC_TRY(ev_stage.init());
-  KC_TRY(ev_sched.init());
-  KC_TRY(ev_list.init());
-  KC_HIP(hipEventRecord(ev_stage.a, st));
+  KC_TRY(ev_stage.init(timed));
+  KC_TRY(ev_sched.init(timed));
+  KC_TRY(ev_list.init(timed));
+  KC_TRY(ev_stage.start(st));
 
   RootInfo ri;
   int64_t *bwords, *pwords;
@@ -1666,8 +1678,8 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   KC_HIP(hipGetLastError());
   int64_t* totals;
   KC_TRY(scr.get(&totals, 4));
-  KC_TRY(kc_scan_i64(bwords, ri.boff, R, totals, st));
-  KC_TRY(kc_scan_i64(pwords, ri.poff, R, totals + 1, st));
+  KC_TRY(kc_scan_i64(bwords, ri.boff, R, totals, scr, st));
+  KC_TRY(kc_scan_i64(pwords, ri.poff, R, totals + 1, scr, st));
   int64_t htot[2];
   int hflags = 0;
   KC_HIP(hipMemcpyAsync(htot, totals, sizeof(htot), hipMemcpyDeviceToHost, st));
@@ -1717,14 +1729,14 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), bytes, st, sa, byclass + hoff[cl], cnt, WM);
     KC_HIP(hipGetLastError());
   }
-  KC_HIP(hipEventRecord(ev_stage.b, st));
+  KC_TRY(ev_stage.stop(st));
   if (c.root_features) {
     k_scatter_features<<<(R * 4 + 255) / 256, 256, 0, st>>>(R, c.roots, feat, c.root_features);
     KC_HIP(hipGetLastError());
   }
 
   // ---- schedule
-  KC_HIP(hipEventRecord(ev_sched.a, st));
+  KC_TRY(ev_sched.start(st));
   float *pred = nullptr, *logw;
   int32_t* depth;
   KC_TRY(scr.get(&logw, R));
@@ -1750,6 +1762,9 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   KC_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * hh.size(), hipMemcpyDeviceToHost, st));
   KC_HIP(hipStreamSynchronize(st));
   const int slots = kc_device_cus() * 4;
+  // split policy: shares of the class's estimated work (2) or fixed counts (1)
+  const int policy = opt && opt->split_policy > 0 ? opt->split_policy : (learned ? 2 : 1);
+  if (policy > 2) return KC_EINVAL;
   ClassBins cb;
   for (int cl = 0; cl < KC_NCLASS; ++cl) {
     const int32_t* h = hh.data() + cl * KC_LOGW_BINS;
@@ -1757,8 +1772,8 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     if (opt && opt->split_threshold > 0.f) {
       lo_bin = (int)(opt->split_threshold * KC_LOGW_SCALE);
       hi_bin = (int)((opt->split_threshold + 4.0f) * KC_LOGW_SCALE);
-    } else if (learned) {
-      // the class's predicted work; a root heavier than 1/(8 slots) of it is
+    } else if (policy == 2) {
+      // the class's estimated work; a root heavier than 1/(8 slots) of it is
       // split once, one heavier than 64 such shares twice
       double tot = 0.0;
       for (int b = 0; b < KC_LOGW_BINS; ++b) tot += (double)h[b] * exp((b + 0.5) / KC_LOGW_SCALE);
@@ -1768,7 +1783,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
         hi_bin = (int)(log(target * 64.0) * KC_LOGW_SCALE) + 1;
       }
     } else {
-      // degree schedule: in each class the slots/4 roots of largest d+ are
+      // fixed counts: in each class the slots/4 roots of highest key are
       // split twice and the next 4 x slots once
       const int64_t n2 = slots / 4, n1 = (int64_t)slots * 4;
       int64_t cum = 0;
@@ -1849,7 +1864,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     k_gather_tasks<<<(NT + 255) / 256, 256, 0, st>>>(tasks, order, NT, tasks_sorted);
     KC_HIP(hipGetLastError());
   }
-  KC_HIP(hipEventRecord(ev_sched.b, st));
+  KC_TRY(ev_sched.stop(st));
 
   // ---- listing: one persistent launch per bitmap class, heaviest first
   unsigned long long* heads;
@@ -1911,8 +1926,9 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     c.capture->destroy = bitcol_replay_destroy;
     return KC_OK;
   }
+  if (c.size_only) return KC_OK;  // every allocation of the call is made
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * KC_NCLASS, st));
-  KC_HIP(hipEventRecord(ev_list.a, st));
+  KC_TRY(ev_list.start(st));
   int launches = 0;
   EventPair ev_cls[KC_NCLASS];
   KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * KC_NCTR * KC_NCLASS, st));
@@ -1933,23 +1949,29 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
       }
     }
   } cs;
-  hipEvent_t ready;
-  KC_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-  struct EvGuard { hipEvent_t e; ~EvGuard() { (void)hipEventDestroy(e); } } ready_guard{ready};
-  KC_HIP(hipEventRecord(ready, st));
+  struct EvGuard {
+    hipEvent_t e = nullptr;
+    ~EvGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } ready;
+  if (cmode == 2) {
+    KC_HIP(hipEventCreateWithFlags(&ready.e, hipEventDisableTiming));
+    KC_HIP(hipEventRecord(ready.e, st));
+  }
   for (int cl = KC_NCLASS - 1; cl >= 0; --cl) {
     if (las[cl].ntasks <= 0) continue;
     hipStream_t ls = st;
     if (cmode == 2) {
       KC_HIP(hipStreamCreateWithFlags(&cs.s[cl], hipStreamNonBlocking));
       KC_HIP(hipEventCreateWithFlags(&cs.done[cl], hipEventDisableTiming));
-      KC_HIP(hipStreamWaitEvent(cs.s[cl], ready, 0));
+      KC_HIP(hipStreamWaitEvent(cs.s[cl], ready.e, 0));
       ls = cs.s[cl];
     }
-    KC_TRY(ev_cls[cl].init());
-    KC_HIP(hipEventRecord(ev_cls[cl].a, ls));
+    KC_TRY(ev_cls[cl].init(timed));
+    KC_TRY(ev_cls[cl].start(ls));
     KC_TRY(launch_list_class(las[cl], cl, nws[cl], pv, ls));
-    KC_HIP(hipEventRecord(ev_cls[cl].b, ls));
+    KC_TRY(ev_cls[cl].stop(ls));
     if (cmode == 2) {
       KC_HIP(hipEventRecord(cs.done[cl], ls));
       KC_HIP(hipStreamWaitEvent(st, cs.done[cl], 0));
@@ -1958,7 +1980,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   }
   k_add_counters<<<1, 64, 0, st>>>(cls_ctr, KC_NCLASS, c.counters);
   KC_HIP(hipGetLastError());
-  KC_HIP(hipEventRecord(ev_list.b, st));
+  KC_TRY(ev_list.stop(st));
   if (c.stats) {
     c.stats->stage_ms += ev_stage.ms();
     c.stats->sched_ms += ev_sched.ms();

@@ -117,12 +117,24 @@ struct kc_dev_graph {
   const int32_t* col;
 };
 
-// Stream-ordered scratch allocation that is released at scope exit.
+// Device scratch of one call.  Either stream-ordered allocations released at
+// scope exit, or sub-allocations (256-byte aligned, bump pointer) of a
+// caller-owned arena that is never freed here.  Every allocation of a call
+// goes through one kc_scratch and none is released before the call ends, so
+// the arena a call needs is the sum of its aligned requests (`need`), which a
+// size query obtains by running the call's preparation (kc_list_ctx.size_only).
+#define KC_SCRATCH_ALIGN 256
 struct kc_scratch {
   hipStream_t stream = nullptr;
-  void* ptrs[128];
-  int count = 0;
+  void** ptrs = nullptr;   // stream-ordered allocations to free
+  int count = 0, cap = 0;
+  char* arena = nullptr;   // caller-owned memory (nullable)
+  size_t arena_bytes = 0;
+  size_t need = 0;         // bytes an arena would need for the requests so far
   explicit kc_scratch(hipStream_t s) : stream(s) {}
+  kc_scratch(hipStream_t s, void* mem, size_t bytes) : stream(s), arena((char*)mem), arena_bytes(bytes) {}
+  kc_scratch(const kc_scratch&) = delete;
+  kc_scratch& operator=(const kc_scratch&) = delete;
   ~kc_scratch();
   int alloc(void** p, size_t bytes);
   template <class T>
@@ -131,9 +143,10 @@ struct kc_scratch {
   }
 };
 
-// Exclusive prefix sums on the device (n elements; out may alias in).
-int kc_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s);
-int kc_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s);
+// Exclusive prefix sums on the device (n elements; out may alias in); the
+// temporaries come from `scr`.
+int kc_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, kc_scratch& scr, hipStream_t s);
+int kc_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, kc_scratch& scr, hipStream_t s);
 
 // Preprocessing (kc_prep.hip).
 struct kc_prep_out {
@@ -174,6 +187,7 @@ struct kc_list_ctx {
   const kc_options* opt;
   kc_stats* stats;
   struct kc_capture* capture;  // non-null: prepare only, hand the listing phase over
+  bool size_only;              // stop before the listing launches (workspace size query)
 };
 
 // A prepared call's listing phase, to be captured into a HIP graph and

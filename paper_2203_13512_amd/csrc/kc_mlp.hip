@@ -5,9 +5,11 @@
 // Inference: one thread per row with the parameters staged in LDS (every lane
 // reads the same weight at the same time, an LDS broadcast).  Training: a row
 // kernel computes activations and the per-row gradients of the pre-activations;
-// a reduction kernel forms each parameter's gradient as a sum over the rows
-// (one thread per parameter, a fixed summation order, so results are
-// reproducible); an update kernel applies Adam.
+// two reduction kernels form each parameter's gradient as a sum over the rows
+// (partial sums per chunk of rows, then the partials in chunk order: a fixed
+// summation order, so results are reproducible); an update kernel applies
+// Adam.  Scratch (the per-row buffer and the partials) comes from the caller's
+// workspace when one is given.
 #include <hip/hip_runtime.h>
 
 #include "kc_internal.h"
@@ -111,19 +113,19 @@ __global__ __launch_bounds__(256) void k_mlp_rows(const float* __restrict__ para
   for (int i = 0; i < H; ++i) o[2 * H + i] = h1[i] > 0.f ? dh1[i] : 0.f;  // dz1
 }
 
-// One thread per parameter: its gradient as a sum over rows, and the loss.
-__global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ x, const float* __restrict__ rowbuf,
-                                                  int32_t rows, float* __restrict__ grad, float* loss) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
+// Gradients as sums over rows, in two passes with a fixed summation order
+// (results are reproducible): each (parameter, chunk of MLP_CHUNK rows) pair
+// is one thread's partial sum, then one thread per parameter adds its
+// partials in chunk order.  Slot P_N carries the squared-error sum (loss).
+#define MLP_CHUNK 256
+__global__ __launch_bounds__(256) void k_mlp_grad_part(const float* __restrict__ x, const float* __restrict__ rowbuf,
+                                                       int32_t rows, float* __restrict__ part) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > P_N) return;
+  const int32_t r0 = (int32_t)blockIdx.y * MLP_CHUNK;
+  const int32_t r1 = r0 + MLP_CHUNK < rows ? r0 + MLP_CHUNK : rows;
   float g = 0.f;
-  if (p == P_N) {
-    // loss = mean squared error
-    for (int32_t r = 0; r < rows; ++r) g += rowbuf[(int64_t)r * ROWW + 4 * H + 1];
-    *loss = g / (float)(rows > 0 ? rows : 1);
-    return;
-  }
-  for (int32_t r = 0; r < rows; ++r) {
+  for (int32_t r = r0; r < r1; ++r) {
     const float* o = rowbuf + (int64_t)r * ROWW;
     float v;
     if (p < P_B1) {
@@ -138,12 +140,31 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float* __restrict__ x, c
       v = o[3 * H + (p - P_B2)];
     } else if (p < P_B3) {
       v = o[4 * H] * o[H + (p - P_W3)];
-    } else {
+    } else if (p == P_B3) {
       v = o[4 * H];
+    } else {
+      v = o[4 * H + 1];  // squared error of the row
     }
     g += v;
   }
-  grad[p] = g;
+  part[(int64_t)blockIdx.y * (P_N + 1) + p] = g;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_grad_sum(const float* __restrict__ part, int32_t nchunks, int32_t rows,
+                                                      float* __restrict__ grad, float* loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > P_N) return;
+  float g = 0.f;
+  for (int32_t c = 0; c < nchunks; ++c) g += part[(int64_t)c * (P_N + 1) + p];
+  if (p == P_N) *loss = g / (float)(rows > 0 ? rows : 1);
+  else grad[p] = g;
+}
+
+static size_t mlp_align(size_t b) { return (b + 255) & ~(size_t)255; }
+static size_t mlp_rowbuf_bytes(int32_t rows) { return mlp_align(sizeof(float) * (size_t)rows * ROWW); }
+static size_t mlp_part_bytes(int32_t rows) {
+  const size_t nchunks = ((size_t)rows + MLP_CHUNK - 1) / MLP_CHUNK;
+  return mlp_align(sizeof(float) * nchunks * (P_N + 1));
 }
 
 __global__ void k_mlp_adam(float* __restrict__ params, const float* __restrict__ grad, float* __restrict__ m,
@@ -166,21 +187,30 @@ extern "C" int kc_mlp_forward(const float* params, const float* x, int32_t rows,
   return kc_mlp_forward_dev(params, x, rows, y, (hipStream_t)stream);
 }
 
+extern "C" int kc_mlp_workspace_size(int32_t rows, size_t* bytes) {
+  if (!bytes || rows < 0) return KC_EINVAL;
+  *bytes = mlp_rowbuf_bytes(rows) + mlp_part_bytes(rows);
+  return KC_OK;
+}
+
 extern "C" int kc_mlp_train_step(float* params, const float* x, const float* target, int32_t rows, float* grad,
-                                 float* loss_out, float* m, float* v, int32_t t, float lr, void* stream) {
+                                 float* loss_out, float* m, float* v, int32_t t, float lr, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
   if (rows <= 0 || !params || !x || !target || !grad || !loss_out) return KC_EINVAL;
   if (lr > 0.f && (!m || !v || t < 1)) return KC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  float* rowbuf = nullptr;
-  KC_HIP(hipMallocAsync((void**)&rowbuf, sizeof(float) * (size_t)rows * ROWW, s));
+  const size_t need = mlp_rowbuf_bytes(rows) + mlp_part_bytes(rows);
+  kc_scratch scr(s, workspace, workspace ? workspace_bytes : 0);
+  if (workspace && workspace_bytes < need) return KC_EWORKSPACE;
+  float *rowbuf = nullptr, *part = nullptr;
+  KC_TRY(scr.alloc((void**)&rowbuf, mlp_rowbuf_bytes(rows)));
+  KC_TRY(scr.alloc((void**)&part, mlp_part_bytes(rows)));
+  const int32_t nchunks = (rows + MLP_CHUNK - 1) / MLP_CHUNK;
+  const unsigned pblocks = (P_N + 1 + 255) / 256;
   k_mlp_rows<<<(rows + 255) / 256, 256, 0, s>>>(params, x, target, rows, rowbuf);
-  k_mlp_grad<<<(P_N + 1 + 255) / 256, 256, 0, s>>>(x, rowbuf, rows, grad, loss_out);
+  k_mlp_grad_part<<<dim3(pblocks, (unsigned)nchunks), 256, 0, s>>>(x, rowbuf, rows, part);
+  k_mlp_grad_sum<<<pblocks, 256, 0, s>>>(part, nchunks, rows, grad, loss_out);
   if (lr > 0.f) k_mlp_adam<<<(P_N + 255) / 256, 256, 0, s>>>(params, grad, m, v, t, lr);
-  hipError_t e = hipGetLastError();
-  (void)hipFreeAsync(rowbuf, s);
-  if (e != hipSuccess) {
-    kc_set_hip_error(e, "mlp train kernels", __FILE__, __LINE__);
-    return KC_EDEVICE;
-  }
+  KC_HIP(hipGetLastError());
   return KC_OK;
 }

@@ -29,13 +29,30 @@ void kc_set_hip_error(hipError_t e, const char* what, const char* file, int line
 
 kc_scratch::~kc_scratch() {
   for (int i = 0; i < count; ++i) (void)hipFreeAsync(ptrs[i], stream);
+  free(ptrs);
 }
 int kc_scratch::alloc(void** p, size_t bytes) {
-  if (count >= 128) return KC_ENOMEM;
+  *p = nullptr;
   if (bytes == 0) bytes = 16;
+  bytes = (bytes + KC_SCRATCH_ALIGN - 1) & ~(size_t)(KC_SCRATCH_ALIGN - 1);
+  const size_t at = need;
+  need += bytes;
+  if (arena) {
+    if (need > arena_bytes) return KC_EWORKSPACE;
+    *p = arena + at;
+    return KC_OK;
+  }
+  if (count == cap) {
+    const int ncap = cap ? 2 * cap : 64;
+    void** np = (void**)realloc(ptrs, sizeof(void*) * (size_t)ncap);
+    if (!np) return KC_ENOMEM;
+    ptrs = np;
+    cap = ncap;
+  }
   hipError_t e = hipMallocAsync(p, bytes, stream);
   if (e != hipSuccess) {
     kc_set_hip_error(e, "hipMallocAsync", __FILE__, __LINE__);
+    *p = nullptr;
     return KC_ENOMEM;
   }
   ptrs[count++] = *p;
@@ -93,42 +110,39 @@ __global__ void k_scan_total(const T* in, const T* out, int64_t n, T* total) {
 }
 
 template <class T>
-static int scan_impl(const T* in, T* out, int64_t n, T* total_dev, hipStream_t s) {
+static int scan_impl(const T* in, T* out, int64_t n, T* total_dev, kc_scratch& scr, hipStream_t s) {
   if (n <= 0) {
     if (total_dev) KC_HIP(hipMemsetAsync(total_dev, 0, sizeof(T), s));
     return KC_OK;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
   // the last input value is needed for the total; keep it before `out` may
-  // overwrite an aliased `in`
+  // overwrite an aliased `in`.  The temporaries live until the call ends.
   T* last = nullptr;
-  KC_HIP(hipMallocAsync((void**)&last, sizeof(T) * (size_t)(tiles + 2), s));
+  KC_TRY(scr.get(&last, (size_t)tiles + 2));
   T* sums = last + 1;
   KC_HIP(hipMemcpyAsync(last, in + (n - 1), sizeof(T), hipMemcpyDeviceToDevice, s));
   k_scan_tiles<T><<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(in, out, n, sums);
   KC_HIP(hipGetLastError());
   if (tiles > 1) {
     T* sums_scanned = nullptr;
-    KC_HIP(hipMallocAsync((void**)&sums_scanned, sizeof(T) * (size_t)(tiles + 1), s));
-    int st = scan_impl<T>(sums, sums_scanned, tiles, (T*)nullptr, s);
-    if (st) return st;
+    KC_TRY(scr.get(&sums_scanned, (size_t)tiles + 1));
+    KC_TRY(scan_impl<T>(sums, sums_scanned, tiles, (T*)nullptr, scr, s));
     k_scan_add<T><<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, n, sums_scanned);
     KC_HIP(hipGetLastError());
-    KC_HIP(hipFreeAsync(sums_scanned, s));
   }
   if (total_dev) {
     k_scan_total<T><<<1, 1, 0, s>>>(last, out + (n - 1), 1, total_dev);
     KC_HIP(hipGetLastError());
   }
-  KC_HIP(hipFreeAsync(last, s));
   return KC_OK;
 }
 
-int kc_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, hipStream_t s) {
-  return scan_impl<int32_t>(in, out, n, total_dev, s);
+int kc_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, kc_scratch& scr, hipStream_t s) {
+  return scan_impl<int32_t>(in, out, n, total_dev, scr, s);
 }
-int kc_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, hipStream_t s) {
-  return scan_impl<int64_t>(in, out, n, total_dev, s);
+int kc_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, kc_scratch& scr, hipStream_t s) {
+  return scan_impl<int64_t>(in, out, n, total_dev, scr, s);
 }
 
 // -------------------------------------------------------------- validation
@@ -443,9 +457,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
   KC_TRY(scr.get(&F0, (size_t)n + 1));
   KC_TRY(scr.get(&F1, (size_t)n + 1));
   KC_TRY(scr.get(&counters, 8));
-  int32_t* hcnt = nullptr;
-  KC_HIP(hipHostMalloc((void**)&hcnt, 64, hipHostMallocDefault));
-  struct PinGuard { int32_t* p; ~PinGuard() { if (p) (void)hipHostFree(p); } } pin{hcnt};
+  int32_t hcnt[16];  // host copies of device counters (pageable: the copies are synchronised)
 
   // ---- Pre-Core (Alg. 3)
   KC_HIP(hipMemsetAsync(counters, 0, 8 * sizeof(int32_t), s));
@@ -563,7 +575,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
     k_dag_count<<<grid_for((int64_t)n * KC_WAVE), 256, 0, s>>>(n, g.rp, g.col, out->removed, out->key, out->drp);
     KC_HIP(hipGetLastError());
   }
-  KC_TRY(kc_scan_i32(out->drp, out->drp, n, out->drp + n, s));
+  KC_TRY(kc_scan_i32(out->drp, out->drp, n, out->drp + n, scr, s));
   int32_t dn = 0;
   KC_TRY(read_i32(out->drp + n, &hcnt[2], s));
   dn = hcnt[2];

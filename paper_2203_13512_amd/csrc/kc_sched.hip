@@ -35,7 +35,7 @@ int kc_bin_sort(const int32_t* bin_dev, int32_t n, int32_t nbins, int32_t* out_d
     k_bin_hist<<<(n + 255) / 256, 256, 0, s>>>(bin_dev, n, nbins, hist);
     KC_HIP(hipGetLastError());
   }
-  KC_TRY(kc_scan_i32(hist, hist, nbins + 1, nullptr, s));
+  KC_TRY(kc_scan_i32(hist, hist, nbins + 1, nullptr, scr, s));
   KC_HIP(hipMemcpyAsync(host_off, hist, sizeof(int32_t) * ((size_t)nbins + 1), hipMemcpyDeviceToHost, s));
   if (n > 0) {
     k_bin_scatter<<<(n + 255) / 256, 256, 0, s>>>(bin_dev, n, nbins, hist, out_dev);

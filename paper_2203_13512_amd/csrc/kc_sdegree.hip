@@ -322,21 +322,35 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   unsigned long long* heads;
   KC_TRY(scr.get(&heads, SD_NCLASS));
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * SD_NCLASS, st));
-  hipEvent_t e0, e1;
-  hipEvent_t ce[SD_NCLASS][2] = {};
+  // timing events only when statistics are asked for
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr, ce[SD_NCLASS][2] = {};
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      for (auto& p : ce)
+        for (auto& e : p)
+          if (e) (void)hipEventDestroy(e);
+    }
+  } ev;
+  const bool timed = c.stats != nullptr && !c.size_only;
   unsigned long long* cls_ctr;
   KC_TRY(scr.get(&cls_ctr, 3 * SD_NCLASS));
   KC_HIP(hipMemsetAsync(cls_ctr, 0, sizeof(unsigned long long) * 3 * SD_NCLASS, st));
-  KC_HIP(hipEventCreate(&e0));
-  KC_HIP(hipEventCreate(&e1));
-  KC_HIP(hipEventRecord(e0, st));
+  if (timed) {
+    KC_HIP(hipEventCreate(&ev.e0));
+    KC_HIP(hipEventCreate(&ev.e1));
+    KC_HIP(hipEventRecord(ev.e0, st));
+  }
   int launches = 0;
   for (int cl = SD_NCLASS - 1; cl >= 0; --cl) {
     int32_t lo = boff[cl * 64], hi = boff[(cl + 1) * 64];
     if (hi <= lo) continue;
-    KC_HIP(hipEventCreate(&ce[cl][0]));
-    KC_HIP(hipEventCreate(&ce[cl][1]));
-    KC_HIP(hipEventRecord(ce[cl][0], st));
+    if (timed) {
+      KC_HIP(hipEventCreate(&ev.ce[cl][0]));
+      KC_HIP(hipEventCreate(&ev.ce[cl][1]));
+      KC_HIP(hipEventRecord(ev.ce[cl][0], st));
+    }
     SdArgs a;
     a.drp = c.drp;
     a.dcol = c.dcol;
@@ -377,18 +391,20 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     }
     if (grid > a.ntasks) grid = a.ntasks;
     if (grid < 1) grid = 1;
+    if (c.size_only) continue;  // the scratch of every class is allocated above
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), lds_bytes, st, a);
     KC_HIP(hipGetLastError());
-    KC_HIP(hipEventRecord(ce[cl][1], st));
+    if (timed) KC_HIP(hipEventRecord(ev.ce[cl][1], st));
     launches++;
   }
-  KC_HIP(hipEventRecord(e1, st));
+  if (c.size_only) return KC_OK;
+  if (timed) KC_HIP(hipEventRecord(ev.e1, st));
   k_sd_add_counters<<<1, 64, 0, st>>>(cls_ctr, SD_NCLASS, c.counters);
   KC_HIP(hipGetLastError());
   if (c.stats) {
     float ms = 0.f;
-    KC_HIP(hipEventSynchronize(e1));
-    KC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    KC_HIP(hipEventSynchronize(ev.e1));
+    KC_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     c.stats->list_ms += ms;
     c.stats->list_launches += launches;
     c.stats->n_tasks += R;
@@ -396,18 +412,13 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     KC_HIP(hipMemcpyAsync(hc, cls_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));
     for (int cl = 0; cl < SD_NCLASS; ++cl) {
-      if (ce[cl][0]) {
+      if (ev.ce[cl][0]) {
         float t = 0.f;
-        if (hipEventElapsedTime(&t, ce[cl][0], ce[cl][1]) == hipSuccess) c.stats->class_ms[cl] = t;
+        if (hipEventElapsedTime(&t, ev.ce[cl][0], ev.ce[cl][1]) == hipSuccess) c.stats->class_ms[cl] = t;
       }
       c.stats->class_work[cl] = hc[3 * cl + 2];
       c.stats->class_tasks[cl] = boff[(cl + 1) * 64] - boff[cl * 64];
     }
   }
-  for (int cl = 0; cl < SD_NCLASS; ++cl)
-    for (int j = 0; j < 2; ++j)
-      if (ce[cl][j]) (void)hipEventDestroy(ce[cl][j]);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   return KC_OK;
 }

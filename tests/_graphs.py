@@ -117,3 +117,39 @@ def elementary_symmetric(a, k):
         for j in range(k, 0, -1):
             e[j] += e[j - 1] * x
     return e[k]
+
+
+def complete_minus_edge(n, a=0, b=1):
+    """K_n without the edge (a, b): C(n,k) - C(n-2,k-2) k-cliques; a and b lie
+    in C(n-2,k-1) of them, every other vertex in C(n-1,k-1) - C(n-3,k-3)."""
+    return csr(n, [(u, v) for u, v in itertools.combinations(range(n), 2) if {u, v} != {a, b}])
+
+
+def cocktail_party(r):
+    """K_{2 x r}: r pairs, every vertex adjacent to all but its partner
+    (vertex 2i pairs with 2i+1); e_k(2,...,2) = 2^k C(r,k) k-cliques."""
+    n = 2 * r
+    return csr(n, [(u, v) for u, v in itertools.combinations(range(n), 2) if u // 2 != v // 2])
+
+
+_WORKLOADS = {}
+
+
+def workload_cached(cfg):
+    """graphgen.workload(cfg) at full size, generated once per test session."""
+    if cfg not in _WORKLOADS:
+        _WORKLOADS[cfg] = graphgen.workload(cfg)
+    return _WORKLOADS[cfg]
+
+
+def graph_sha(rp, ci):
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(rp, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(ci, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
+def array_sha(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u8").tobytes()).hexdigest()

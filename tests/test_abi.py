@@ -12,7 +12,8 @@ def test_header_declares_the_boundary():
     names = kc.declared_symbols()
     for f in ["kclique_count", "kclique_list_per_vertex", "kclique_count_ex", "kclique_count_batched",
               "kclique_plan_batched", "kclique_plan_execute", "kclique_plan_destroy",
-              "kc_mlp_forward", "kc_mlp_train_step", "kc_status_string", "kc_options_init"]:
+              "kc_mlp_forward", "kc_mlp_train_step", "kc_status_string", "kc_options_init",
+              "kclique_workspace_size", "kc_mlp_workspace_size"]:
         assert f in names
 
 
@@ -25,8 +26,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_without_device():
     lib = kc._lib()
-    for st in (0, -1, -2, -3, -4, -5):
-        assert lib.kc_status_string(st)
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.kc_status_string(st) and lib.kc_status_string(st) != b"unknown status"
 
 
 def test_struct_layouts_match_header():

@@ -1,0 +1,134 @@
+"""Wide local subgraphs: every bitmap word class of the BitCol listing kernel
+(1 to 32 words of 32 bits, local subgraphs of up to 1024 vertices) and every
+candidate-list class of SDegree, including its device-memory lists, against
+closed forms.
+
+K_n minus one edge survives Pre-Core and Pre-List (it is not a clique), and
+under the degeneracy order its roots have every out-degree from 0 to n-2, so
+one graph puts roots into every word class; its k-cliques number
+C(n,k) - C(n-2,k-2).  The cocktail-party graph K_{2 x r} (every vertex
+adjacent to all but its partner) has 2^k C(r,k) of them and 2^(k-1) C(r-1,k-1)
+per vertex.  The statistics' per-class task counts show which word classes
+ran.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from tests import _graphs as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2203_13512_amd as kc  # noqa: E402
+
+WORDS = [1, 2, 4, 8, 12, 16, 24, 32]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(g):
+    rp, ci = g
+    return torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+
+
+def minus_edge_count(n, k):
+    return math.comb(n, k) - math.comb(n - 2, k - 2)
+
+
+def minus_edge_pv(n, k, a=0, b=1):
+    pv = np.full(n, math.comb(n - 1, k - 1) - math.comb(n - 3, k - 3), dtype=np.int64)
+    pv[[a, b]] = math.comb(n - 2, k - 1)
+    return pv
+
+
+def classes_run(st):
+    return [WORDS[c] for c in range(8) if st["class_tasks"][c] > 0]
+
+
+LAUNCH = [dict(), dict(waves_per_root=1), dict(waves_per_root=4, chunk=4), dict(compress=-1),
+          dict(compress=64, compress_level=3), dict(split=1, split_threshold=1.0),
+          dict(split=2, split_threshold=1.0, waves_per_root=8), dict(class_streams=2)]
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_every_word_class_complete_minus_edge(k):
+    n = 1000
+    g = dev(G.complete_minus_edge(n))
+    want = minus_edge_count(n, k)
+    for kw in LAUNCH:
+        say("K_n - e", n, k, kw)
+        c, st = kc.count(*g, k, "color", stats=True, **kw)
+        assert c == want, kw
+        assert classes_run(st) == WORDS, classes_run(st)
+        assert st["max_out_degree"] == n - 2
+
+
+def test_every_word_class_k6_and_learned_schedule():
+    from paper_2203_13512_amd import scheduler
+    n = 400
+    g = dev(G.complete_minus_edge(n, 7, 300))
+    mlp = scheduler.load_model(torch.device("cuda"), 6)
+    for kw in [dict(), dict(schedule="learned", mlp=mlp), dict(compress=-1, waves_per_root=8)]:
+        say("K_n - e", n, 6, {key: v for key, v in kw.items() if key != "mlp"})
+        c, st = kc.count(*g, 6, "color", stats=True, **kw)
+        assert c == minus_edge_count(n, 6)
+        assert classes_run(st) == [1, 2, 4, 8, 12, 16]
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_every_word_class_cocktail_party(k):
+    r = 500
+    g = dev(G.cocktail_party(r))
+    for kw in [dict(), dict(compress=-1), dict(waves_per_root=4, split=2, split_threshold=1.0)]:
+        say("cocktail party", r, k, kw)
+        c, st = kc.count(*g, k, "color", stats=True, **kw)
+        assert c == 2 ** k * math.comb(r, k), kw
+        assert classes_run(st) == WORDS
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_per_vertex_up_to_512_local_vertices(k):
+    n = 514  # out-degrees up to 512: every per-vertex word class (1..16 words)
+    g = dev(G.complete_minus_edge(n, 3, 400))
+    for kw in [dict(), dict(compress=-1), dict(waves_per_root=8, split=1, split_threshold=1.0)]:
+        say("per-vertex K_n - e", n, k, kw)
+        c, pv, st = kc.count(*g, k, "color", per_vertex=True, stats=True, **kw)
+        assert c == minus_edge_count(n, k)
+        assert np.array_equal(pv.cpu().numpy(), minus_edge_pv(n, k, 3, 400)), kw
+        assert classes_run(st) == [1, 2, 4, 8, 12, 16]
+    r = 257
+    c, pv = kc.count(*dev(G.cocktail_party(r)), k, "color", per_vertex=True)
+    assert c == 2 ** k * math.comb(r, k)
+    assert bool((pv == 2 ** (k - 1) * math.comb(r - 1, k - 1)).all())
+
+
+def test_sdegree_device_memory_lists():
+    """Degree order: out-degrees above 1024 take SDegree's candidate-list
+    class whose per-level lists live in device memory instead of LDS."""
+    n = 1030
+    g = dev(G.complete_minus_edge(n))
+    c, st = kc.count(*g, 4, "degree", stats=True)
+    assert c == minus_edge_count(n, 4)
+    assert st["max_out_degree"] == n - 2 and st["class_tasks"][3] > 0
+    c, pv = kc.count(*g, 4, "degree", per_vertex=True)
+    assert c == minus_edge_count(n, 4)
+    assert np.array_equal(pv.cpu().numpy(), minus_edge_pv(n, 4))
+
+
+def test_local_subgraphs_beyond_the_supported_size_are_reported():
+    """Counting takes local subgraphs of up to 1024 vertices, per-vertex
+    output up to 512; larger ones are refused, not truncated."""
+    g = dev(G.complete_minus_edge(1030))
+    with pytest.raises(kc.KCliqueError) as e:
+        kc.count(*g, 4, "color")
+    assert e.value.status == kc.EUNSUPPORTED
+    g = dev(G.complete_minus_edge(520))
+    with pytest.raises(kc.KCliqueError) as e:
+        kc.count(*g, 4, "color", per_vertex=True)
+    assert e.value.status == kc.EUNSUPPORTED

@@ -66,3 +66,23 @@ def test_adam_first_step_closed_form():
     p1, m, v = M.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr)
     assert np.allclose(p1, p - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_gradient_magnitude_bounds_and_equals_the_gradient_when_nothing_cancels():
+    r = np.random.default_rng(6)
+    p = M.init_params(2) + r.normal(0, 0.05, M.NPARAMS)
+    x = r.normal(0, 1, (50, 4))
+    t = r.normal(0, 1, 50)
+    _, g = M.loss_and_grad(p, x, t)
+    ga = M.grad_magnitude(p, x, t)
+    assert np.all(ga >= np.abs(g) - 1e-12)
+    # positive weights and inputs, targets <= 0: every term of every sum has
+    # the same sign, so the magnitude is the gradient itself
+    pp = np.abs(p)
+    xp = np.abs(x)
+    tn = -np.abs(t)
+    _, g2 = M.loss_and_grad(pp, xp, tn)
+    assert np.allclose(M.grad_magnitude(pp, xp, tn), g2, rtol=1e-12, atol=0)
+    # margins: ReLU pre-activations relative to their terms, in [0, 1]
+    m = M.relu_margin(p, x)
+    assert m.shape == (50,) and np.all((m >= 0) & (m <= 1 + 1e-12))

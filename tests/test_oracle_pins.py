@@ -429,3 +429,47 @@ def test_paper_bitcol_trace_on_the_encoded_example():
         assert int(per["colors"][0]) == 4 and int(per["edges"][0]) == 12, k
         sub = oracle.bitcol_roots(drp, dci, k, [0])
         assert [int(sub[key][0]) for key in ("count", "isect", "nodes", "words")] == [cnt, joins, calls, joins]
+
+
+def test_sdegree_roots_matches_the_whole_dag_run():
+    """The per-root SDegree entry point (used for sliced runs on large graphs)
+    returns exactly the whole-DAG run's per-root values."""
+    g = graphgen.chung_lu(3000, 12.0, 2.1, 300.0, planted=[18, 12], seed=6)
+    for k in (4, 6):
+        rem = oracle.precore(*g, k)
+        rem, _, _, _ = oracle.prelist(*g, k, rem)
+        drp, dci = oracle.degree_dag(*g, rem)
+        total, per = oracle.sdegree_dag(drp, dci, k)
+        roots = np.flatnonzero(np.diff(drp) >= k - 1)[::2]
+        sub = oracle.sdegree_roots(drp, dci, k, roots)
+        for key in ("count", "nodes", "isect", "elems"):
+            assert np.array_equal(sub[key], per[key][roots]), key
+
+
+@pytest.mark.parametrize("n,a,b", [(9, 0, 1), (14, 2, 5), (20, 19, 3)])
+def test_complete_minus_edge_closed_form(n, a, b):
+    """K_n without one edge: C(n,k) - C(n-2,k-2) cliques; its endpoints lie in
+    C(n-2,k-1), every other vertex in C(n-1,k-1) - C(n-3,k-3); the methods as
+    the paper orders them reach the same."""
+    rp, ci = G.complete_minus_edge(n, a, b)
+    for k in range(3, n + 1):
+        want = math.comb(n, k) - math.comb(n - 2, k - 2)
+        c, pv = oracle.count(rp, ci, k, per_vertex=True)
+        assert c == want
+        for v in range(n):
+            exp = math.comb(n - 2, k - 1) if v in (a, b) else math.comb(n - 1, k - 1) - math.comb(n - 3, k - 3)
+            assert int(pv[v]) == exp
+        for method in ("degree", "color"):
+            assert oracle.method_count(rp, ci, k, method)[0] == want
+
+
+@pytest.mark.parametrize("r", [3, 6, 9])
+def test_cocktail_party_closed_form(r):
+    rp, ci = G.cocktail_party(r)
+    for k in range(1, r + 2):
+        c, pv = oracle.count(rp, ci, k, per_vertex=True)
+        assert c == 2 ** k * math.comb(r, k)
+        assert all(int(x) == 2 ** (k - 1) * math.comb(r - 1, k - 1) for x in pv)
+        if k >= 3:
+            for method in ("degree", "color"):
+                assert oracle.method_count(rp, ci, k, method)[0] == c
