@@ -46,7 +46,7 @@ extern "C" {
 
 typedef enum {
   KC_OK = 0,
-  KC_EINVAL = -1,        /* malformed graph, k < 1, unknown order/schedule */
+  KC_EINVAL = -1,        /* malformed graph, k < 1, unknown order/schedule/option */
   KC_ENOMEM = -2,        /* device allocation failed */
   KC_EOVERFLOW = -3,     /* a count does not fit in 64 bits (e.g. C(201,20)) */
   KC_EDEVICE = -4,       /* a HIP runtime call failed or no device */
@@ -57,6 +57,16 @@ typedef enum {
 /* Orientation / algorithm. */
 #define KC_ORDER_DEGREE 0 /* SDegree: degree order, sorted-list merge joins (Alg. 5) */
 #define KC_ORDER_COLOR 1  /* BitCol: degeneracy order + per-root color order, bitmaps (Alg. 6) */
+#define KC_ORDER_CORE 2   /* SDegree's merge joins (Alg. 5) on the degeneracy order: Sec. 6.2 notes that
+                             SDegree can take any vertex order; out-degrees are then bounded by core numbers */
+
+/* Ablations (kc_options.disable, bit mask; Sec. 9.2 and 9.4 compare the
+ * method with and without its preprocessing and pruning).  None changes a
+ * result, only the work done. */
+#define KC_NO_PRECORE 1 /* skip Pre-Core (Alg. 3) */
+#define KC_NO_PRELIST 2 /* skip Pre-List (Alg. 4) */
+#define KC_NO_PRUNE 4   /* SDegree: no d+ <= l-2 skip and no |C'| > l-2 test (children with any member are
+                           entered); BitCol: no color(v) < l skip (Sec. 7.1; its size test stays) */
 
 /* Root schedule of the persistent listing kernel (does not change results). */
 #define KC_SCHED_DEGREE 0  /* roots ordered and split by DAG out-degree */
@@ -113,6 +123,7 @@ typedef struct {
   int32_t class_streams;  /* BitCol: listing kernels of the word classes 1 = one after another on `stream`,
                              2 = concurrently on streams of their own, 0 = auto (1 for the learned
                              schedule, 2 for the degree schedule) */
+  int32_t disable;        /* ablation bit mask of KC_NO_PRECORE, KC_NO_PRELIST, KC_NO_PRUNE (0 = the method) */
   int32_t split_policy;   /* BitCol: which roots are split into depth-1 / depth-2 work items, given each
                              root's work estimate (the schedule's key).  0 = the schedule's own (2 for
                              LEARNED, 1 for DEGREE); 1 = fixed counts: per word class the slots/4
@@ -160,6 +171,23 @@ int kclique_list_per_vertex(int32_t n, const int32_t* row_ptr, const int32_t* co
  * memory. */
 int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                      const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out);
+
+/* Listing (Sec. 3.1: report every k-clique of G).  Each k-clique is written
+ * exactly once (Theorem 1) as a row of k int32 vertex ids -- the emit steps of
+ * Alg. 5 (SDegree, R + {u, v} at l = 2) and Alg. 6 (BitCol, R + {v, w} at
+ * l = 2), and, for the clique components Pre-List removes (Alg. 4), each of
+ * their k-subsets.  cliques_out holds `capacity` rows, row-major (capacity x k
+ * int32; device memory if opt->device_ptrs, else host); the order of the
+ * rows and of the ids inside a row is unspecified.  *count_out receives the
+ * total number of k-cliques and *written_out the rows written,
+ * min(total, capacity): when the total exceeds the capacity the rows written
+ * are some `capacity` of the cliques (the count is still exact).  k >= 1 (k =
+ * 1: one row per vertex; k = 2: one row (u, v), u < v, per edge).  Options as
+ * for kclique_count_ex; the schedule, the per-root logs and vertex_k do not
+ * apply (vertex_k gives KC_EINVAL). */
+int kclique_list(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                 const kc_options* opt, int32_t* cliques_out, int64_t capacity, int64_t* written_out,
+                 uint64_t* count_out);
 
 /* Scratch memory a kclique_count_ex call with the same arguments and options
  * needs when it takes it from kc_options.workspace; per_vertex = 1 when that

@@ -58,6 +58,7 @@ def _load():
         "orc_count_idorder": [i32, vp, vp, i32, vp, vp],
         "orc_count_idorder_roots": [i32, vp, vp, i32, vp, i32, dbl, vp, vp, vp],
         "orc_vertex_count": [i32, vp, vp, i32, i32, u64, vp],
+        "orc_list_idorder": [i32, vp, vp, i32, vp, i64, vp, vp],
         "orc_core_numbers": [i32, vp, vp, vp],
         "orc_precore": [i32, vp, vp, i32, vp],
         "orc_prelist": [i32, vp, vp, i32, vp, vp, vp, vp],
@@ -70,7 +71,7 @@ def _load():
         "orc_bitcol_roots": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp],
         "orc_sdegree_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
-        "orc_method_count": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "orc_method_count": [i32, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -144,6 +145,20 @@ def count_roots(rp, ci, k: int, roots, seconds: float = 0.0):
     if st not in (OK, EBUDGET):
         _check(st, "count_roots")
     return int(c[0]), int(done[0]), st == OK
+
+
+def list_cliques(rp, ci, k: int, capacity: int | None = None):
+    """Every k-clique as a row of ascending vertex ids (rows in the order of
+    the ordered recursion, i.e. lexicographic).  Returns (rows, total)."""
+    rp, ci = _csr(rp, ci)
+    n = len(rp) - 1
+    if capacity is None:
+        capacity = count(rp, ci, k)
+    out = np.zeros(max(capacity * k, 1), dtype=np.int32)
+    written = np.zeros(1, dtype=np.int64)
+    total = np.zeros(1, dtype=np.uint64)
+    _check(_load().orc_list_idorder(n, _p(rp), _p(ci), k, _p(out), capacity, _p(written), _p(total)), "list_cliques")
+    return out[: int(written[0]) * k].reshape(-1, k), int(total[0])
 
 
 def vertex_count(rp, ci, k: int, v: int, budget: int = 0):
@@ -290,18 +305,20 @@ def bitcol_roots(drp, dci, k: int, roots, L: int = 32):
     return dict(zip(["count", "nodes", "isect", "words"], [a[:len(roots)] for a in u]))
 
 
-def method_count(rp, ci, k: int, method: str, L: int = 32):
-    """Whole SDegree ('degree') or BitCol ('color') pipeline as the paper orders
-    it.  Returns (total, prelist_count, per_root dict)."""
+def method_count(rp, ci, k: int, method: str, L: int = 32, disable: int = 0):
+    """Whole SDegree ('degree'), BitCol ('color') or SDegree-on-degeneracy
+    ('core') pipeline as the paper orders it; `disable` skips Pre-Core (1),
+    Pre-List (2) or the pruning (4).  Returns (total, prelist_count,
+    per_root dict)."""
     rp, ci = _csr(rp, ci)
     n = len(rp) - 1
-    m = {"degree": 0, "color": 1}[method]
+    m = {"degree": 0, "color": 1, "core": 2}[method]
     c = np.zeros(1, dtype=np.uint64)
     pl = np.zeros(1, dtype=np.uint64)
     u = [np.zeros(max(n, 1), dtype=np.uint64) for _ in range(4)]
     i3 = [np.zeros(max(n, 1), dtype=np.int32) for _ in range(3)]
     e = np.zeros(max(n, 1), dtype=np.int64)
-    st = _load().orc_method_count(n, _p(rp), _p(ci), k, m, L, _p(c), _p(pl), *[_p(a) for a in u],
+    st = _load().orc_method_count(n, _p(rp), _p(ci), k, m, L, disable, _p(c), _p(pl), *[_p(a) for a in u],
                                   *[_p(a) for a in i3], _p(e))
     _check(st, "method_count")
     d = dict(zip(["count", "nodes", "isect", "work"], [a[:n] for a in u]))

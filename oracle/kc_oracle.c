@@ -21,6 +21,7 @@
  *                        (the kClist scheme of Alg. 2 with eta = vertex id):
  *                        each clique is counted once, from its smallest id.
  *                        Optional per-vertex participation counts.
+ *   orc_list_idorder     listing: the same recursion writing each clique's ids.
  *   orc_vertex_count     per-vertex participation of one vertex v: the number
  *                        of (k-1)-cliques in the subgraph induced by N(v).
  *   orc_core_numbers     core numbers by the bucket algorithm of Batagelj and
@@ -283,6 +284,82 @@ int orc_count_idorder(int32_t n, const int32_t* rp, const int32_t* col, int32_t 
   return orc_count_idorder_roots(n, rp, col, k, NULL, 0, 0.0, count, pv, NULL);
 }
 
+/* Listing (Sec. 3.1): every k-clique as its k vertex ids in ascending order,
+ * by the same ordered recursion (each clique reached once, from its smallest
+ * id, then in ascending id order).  Rows go to out[cap][k] in the order the
+ * recursion meets them; *written receives min(count, cap), *count the total. */
+typedef struct {
+  const int32_t* rp;
+  const int32_t* col;
+  int32_t k;
+  int32_t* R;
+  int32_t* buf;
+  int32_t stride;
+  int32_t* out;
+  int64_t cap, rows;
+} idlist_t;
+
+static void idlist(idlist_t* S, int32_t l, const int32_t* cand, int32_t len, int32_t depth) {
+  if (l == 0) {
+    if (S->rows < S->cap)
+      for (int32_t i = 0; i < S->k; ++i) S->out[S->rows * S->k + i] = S->R[i];
+    S->rows++;
+    return;
+  }
+  int32_t* next = S->buf + (size_t)(depth + 1) * (size_t)S->stride;
+  for (int32_t i = 0; i < len; ++i) {
+    int32_t v = cand[i];
+    /* next = {w in N(v) : w > v} intersected with cand[i+1..len) */
+    int32_t a = S->rp[v], ae = S->rp[v + 1], b = i + 1, m = 0;
+    while (a < ae && S->col[a] <= v) a++;
+    while (a < ae && b < len) {
+      int32_t x = S->col[a], y = cand[b];
+      if (x == y) { next[m++] = x; a++; b++; }
+      else if (x < y) a++;
+      else b++;
+    }
+    if (m < l - 1) continue;
+    S->R[depth] = v;
+    idlist(S, l - 1, next, m, depth + 1);
+  }
+}
+
+int orc_list_idorder(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, int32_t* out, int64_t cap,
+                     int64_t* written, uint64_t* count) {
+  if (n < 0 || k < 1 || cap < 0) return ORC_EINVAL;
+  *written = 0;
+  *count = 0;
+  if (n == 0) return ORC_OK;
+  idlist_t S;
+  memset(&S, 0, sizeof(S));
+  S.rp = rp;
+  S.col = col;
+  S.k = k;
+  S.out = out;
+  S.cap = cap;
+  S.stride = max_degree(n, rp) + 1;
+  S.R = (int32_t*)malloc(sizeof(int32_t) * ((size_t)k + 1));
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
+  if (!S.R || !S.buf) { free(S.R); free(S.buf); return ORC_ENOMEM; }
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t m = 0;
+    for (int32_t i = rp[u]; i < rp[u + 1]; ++i)
+      if (col[i] > u) S.buf[m++] = col[i];
+    S.R[0] = u;
+    if (k == 1) {
+      if (S.rows < S.cap) S.out[S.rows * k] = u;
+      S.rows++;
+      continue;
+    }
+    idlist(&S, k - 1, S.buf, m, 1);
+  }
+  free(S.R);
+  free(S.buf);
+  *count = (uint64_t)S.rows;
+  *written = S.rows < cap ? S.rows : cap;
+  return ORC_OK;
+}
+
 /* Participation of vertex v: (k-1)-cliques inside G[N(v)].  `budget` caps the
  * number of intersections (0 = unlimited); ORC_EBUDGET when exceeded. */
 int orc_vertex_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, int32_t v, uint64_t budget,
@@ -510,6 +587,7 @@ typedef struct {
   int32_t* buf;
   uint64_t count, nodes, isect, elems;
   int status;
+  int noprune; /* ablation: no d+ <= l-2 skip, recurse into any non-empty C' */
 } sdeg_t;
 
 static int32_t merge_join(const int32_t* a, int32_t na, const int32_t* b, int32_t nb, int32_t* out) {
@@ -533,13 +611,13 @@ static void sdegree_list(sdeg_t* S, int32_t l, const int32_t* C, int32_t nc, int
   for (int32_t i = 0; i < nc && !S->status; ++i) {
     int32_t u = C[i];
     int32_t du = S->drp[u + 1] - S->drp[u];
-    if (du <= l - 2) continue;
+    if (!S->noprune && du <= l - 2) continue;
     int32_t m = merge_join(S->dcol + S->drp[u], du, C, nc, next);
     S->isect++;
     S->elems += (uint64_t)nc + (uint64_t)du;
     if (l == 2) {
       if (add_checked(&S->count, (uint64_t)m)) S->status = ORC_EOVERFLOW;
-    } else if (m > l - 2) {
+    } else if (S->noprune ? m > 0 : m > l - 2) {
       sdegree_list(S, l - 1, next, m, depth + 1);
     }
   }
@@ -547,8 +625,16 @@ static void sdegree_list(sdeg_t* S, int32_t l, const int32_t* C, int32_t nc, int
 
 /* SDegree on a DAG.  Per root u (index = vertex id) the arrays receive the
  * cliques found from u and the work counters (any may be NULL).  k >= 3. */
+static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, uint64_t* count,
+                       uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems);
+
 int orc_sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, uint64_t* count,
                     uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
+  return sdegree_dag(n, drp, dcol, k, 0, count, root_count, root_nodes, root_isect, root_elems);
+}
+
+static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, uint64_t* count,
+                       uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
   if (n < 0 || k < 3) return ORC_EINVAL;
   *count = 0;
   int32_t md = 0;
@@ -558,6 +644,7 @@ int orc_sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t 
   memset(&S, 0, sizeof(S));
   S.drp = drp;
   S.dcol = dcol;
+  S.noprune = noprune;
   S.stride = md + 1;
   S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
   if (!S.buf) return ORC_ENOMEM;
@@ -663,6 +750,7 @@ typedef struct {
   uint32_t* stack;       /* candidate bitmaps, one per depth */
   uint64_t count, nodes, isect, words;
   int status;
+  int noprune;           /* ablation: no color(v) < l skip */
 } bitcol_t;
 
 static int32_t bits_set(const uint32_t* x, int32_t nw) {
@@ -677,7 +765,7 @@ static void bitcol_list(bitcol_t* S, int32_t l, const uint32_t* CB, int32_t dept
   for (int32_t v = 0; v < S->s && !S->status; ++v) {
     /* decode: v is a member of CB */
     if (!((CB[v / S->L] >> (v % S->L)) & 1u)) continue;
-    if (S->color[v] < l) continue;
+    if (!S->noprune && S->color[v] < l) continue;
     const uint32_t* Bv = S->B + (size_t)v * S->nw;
     for (int32_t i = 0; i < S->nw; ++i) next[i] = Bv[i] & CB[i]; /* BitJoin */
     S->isect++;
@@ -790,15 +878,27 @@ static int bitcol_root(bitcol_t* S, bitcol_ws_t* w, const int32_t* drp, const in
 
 /* BitCol on a DAG (normally the degeneracy DAG).  Per root u: cliques found,
  * work counters, and the features d+_u, number of colors of G_u, |E_u|. */
+static int bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, int noprune,
+                      uint64_t* count, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                      uint64_t* root_words, int32_t* root_colors, int64_t* root_edges);
+
 int orc_bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, uint64_t* count,
                    uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_words,
                    int32_t* root_colors, int64_t* root_edges) {
+  return bitcol_dag(n, drp, dcol, k, L, 0, count, root_count, root_nodes, root_isect, root_words, root_colors,
+                    root_edges);
+}
+
+static int bitcol_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L, int noprune,
+                      uint64_t* count, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                      uint64_t* root_words, int32_t* root_colors, int64_t* root_edges) {
   if (n < 0 || k < 3 || L < 1 || L > 32) return ORC_EINVAL;
   *count = 0;
   bitcol_ws_t w;
   if (bitcol_ws_init(&w, n, drp, k, L)) return ORC_ENOMEM;
   bitcol_t S;
   memset(&S, 0, sizeof(S));
+  S.noprune = noprune;
   int st = ORC_OK;
   for (int32_t u = 0; u < n && !st; ++u) {
     uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, w0 = S.words;
@@ -847,14 +947,18 @@ int orc_bitcol_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t
 
 /* ------------------------------------------- whole methods (Alg. 5, 6) */
 /* Pre-Core, Pre-List, orientation and listing, as the paper orders them.
- * method 0 = SDegree (degree DAG), 1 = BitCol (degeneracy DAG, L bits).
- * Returns the total count (Pre-List cliques included); the per-root arrays
- * (size n, may be NULL) describe the listing phase only. */
+ * method 0 = SDegree (degree DAG), 1 = BitCol (degeneracy DAG, L bits),
+ * 2 = SDegree on the degeneracy DAG (Sec. 6.2: any vertex order).
+ * disable: ablation bits 1 = skip Pre-Core, 2 = skip Pre-List, 4 = no
+ * pruning (SDegree: no d+ <= l-2 skip, children with any member entered;
+ * BitCol: no color(v) < l skip).  Returns the total count (Pre-List cliques
+ * included); the per-root arrays (size n, may be NULL) describe the listing
+ * phase only. */
 int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k, int32_t method, int32_t L,
-                     uint64_t* count, uint64_t* prelist_count, uint64_t* root_count, uint64_t* root_nodes,
-                     uint64_t* root_isect, uint64_t* root_work, int32_t* root_dplus, int32_t* root_core,
-                     int32_t* root_colors, int64_t* root_edges) {
-  if (n < 0 || k < 3) return ORC_EINVAL;
+                     int32_t disable, uint64_t* count, uint64_t* prelist_count, uint64_t* root_count,
+                     uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_work, int32_t* root_dplus,
+                     int32_t* root_core, int32_t* root_colors, int64_t* root_edges) {
+  if (n < 0 || k < 3 || method < 0 || method > 2) return ORC_EINVAL;
   *count = 0;
   if (prelist_count) *prelist_count = 0;
   if (n == 0) return ORC_OK;
@@ -863,23 +967,27 @@ int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k
   int32_t* dcol = (int32_t*)malloc(sizeof(int32_t) * ((size_t)rp[n] / 2 + 1));
   int32_t* core = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   if (!removed || !drp || !dcol || !core) { free(removed); free(drp); free(dcol); free(core); return ORC_ENOMEM; }
-  int st = orc_precore(n, rp, col, k, removed);
+  int st = ORC_OK;
+  if (disable & 1) memset(removed, 0, (size_t)n);
+  else st = orc_precore(n, rp, col, k, removed);
   uint64_t pl = 0;
-  if (!st) st = orc_prelist(n, rp, col, k, removed, &pl, NULL, NULL);
+  if (!st && !(disable & 2)) st = orc_prelist(n, rp, col, k, removed, &pl, NULL, NULL);
   if (!st) {
     if (method == 0) st = orc_degree_dag(n, rp, col, removed, drp, dcol);
     else st = orc_degeneracy_dag(n, rp, col, removed, drp, dcol, NULL, core);
   }
   uint64_t c = 0;
+  const int noprune = (disable & 4) != 0;
   if (!st) {
-    if (method == 0) st = orc_sdegree_dag(n, drp, dcol, k, &c, root_count, root_nodes, root_isect, root_work);
-    else st = orc_bitcol_dag(n, drp, dcol, k, L, &c, root_count, root_nodes, root_isect, root_work, root_colors,
-                             root_edges);
+    if (method == 1)
+      st = bitcol_dag(n, drp, dcol, k, L, noprune, &c, root_count, root_nodes, root_isect, root_work, root_colors,
+                      root_edges);
+    else st = sdegree_dag(n, drp, dcol, k, noprune, &c, root_count, root_nodes, root_isect, root_work);
   }
   if (!st) {
     if (root_dplus)
       for (int32_t u = 0; u < n; ++u) root_dplus[u] = drp[u + 1] - drp[u];
-    if (root_core && method == 1) memcpy(root_core, core, sizeof(int32_t) * (size_t)n);
+    if (root_core && method != 0) memcpy(root_core, core, sizeof(int32_t) * (size_t)n);
     if (add_checked(&c, pl)) st = ORC_EOVERFLOW;
   }
   if (!st) {

@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(HERE, "libkclique.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "kclique.h")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
-ORDERS = {"degree": 0, "color": 1}
+ORDERS = {"degree": 0, "color": 1, "core": 2}
+NO_PRECORE, NO_PRELIST, NO_PRUNE = 1, 2, 4
 SCHEDULES = {"degree": 0, "learned": 1}
 MLP_IN, MLP_HIDDEN = 4, 64
 MLP_NPARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -61,7 +62,7 @@ class Options(ctypes.Structure):
         ("schedule", ctypes.c_int32), ("mlp_params", ctypes.c_void_p), ("mlp_norm", ctypes.c_void_p),
         ("waves_per_root", ctypes.c_int32), ("chunk", ctypes.c_int32), ("split", ctypes.c_int32),
         ("split_threshold", ctypes.c_float), ("compress", ctypes.c_int32), ("compress_level", ctypes.c_int32),
-        ("class_streams", ctypes.c_int32), ("split_policy", ctypes.c_int32),
+        ("class_streams", ctypes.c_int32), ("disable", ctypes.c_int32), ("split_policy", ctypes.c_int32),
         ("root_work", ctypes.c_void_p), ("root_isect", ctypes.c_void_p),
         ("root_features", ctypes.c_void_p), ("root_count", ctypes.c_void_p), ("vertex_k", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
@@ -107,6 +108,9 @@ def _lib():
     L.kclique_workspace_size.restype = ctypes.c_int
     L.kclique_workspace_size.argtypes = [i32, vp, vp, i32, i32, i32, ctypes.POINTER(Options),
                                          ctypes.POINTER(ctypes.c_size_t)]
+    L.kclique_list.restype = ctypes.c_int
+    L.kclique_list.argtypes = [i32, vp, vp, i32, i32, ctypes.POINTER(Options), vp, ctypes.c_int64,
+                               ctypes.POINTER(ctypes.c_int64), u64p]
     L.kc_options_init.restype = None
     L.kc_options_init.argtypes = [ctypes.POINTER(Options)]
     _LIB = L
@@ -135,7 +139,7 @@ def _check(st: int, what: str):
 
 
 _OPTION_KEYS = ("waves_per_root", "chunk", "split", "split_threshold", "compress", "compress_level",
-                "class_streams", "split_policy")
+                "class_streams", "split_policy", "disable")
 
 
 def _options(schedule="degree", mlp=None, trusted=False, **launch):
@@ -208,7 +212,7 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
     caller (at least workspace_size() bytes), or "torch" (sized with
     workspace_size() and allocated by torch for this call).  ``launch``:
     waves_per_root, chunk, split, split_threshold, compress, compress_level,
-    class_streams, split_policy (kc_options; none changes a result).
+    class_streams, split_policy, disable (kc_options; none changes a result).
     """
     L = _lib()
     opt, keep = _options(schedule, mlp, trusted, **launch)
@@ -273,6 +277,40 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
         if stats:
             res.append(st.as_dict())
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def list_cliques(row_ptr, col_idx, k: int, order: str = "color", capacity: int | None = None, *,
+                 trusted: bool = False, workspace=None, **launch):
+    """Every k-clique (``kclique_list``): returns (rows, total), rows an
+    int32 array of shape (min(total, capacity), k) of vertex ids (a torch
+    tensor on the GPU for GPU input, numpy otherwise; row order and the order
+    inside a row are unspecified).  Without ``capacity`` the total is counted
+    first and the buffer sized to it."""
+    L = _lib()
+    if capacity is None:
+        capacity = count(row_ptr, col_idx, k, order, trusted=trusted)
+    opt, keep = _options("degree", None, trusted, **launch)
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    written = ctypes.c_int64(0)
+    total = ctypes.c_uint64(0)
+    if _is_torch(row_ptr) and row_ptr.is_cuda:
+        import torch
+        rp, ci = _device_csr(row_ptr, col_idx)
+        opt.device_ptrs = 1
+        opt.stream = _torch_stream(rp.device)
+        out = torch.empty((max(capacity, 1), k), dtype=torch.int32, device=rp.device)
+        rc = L.kclique_list(rp.numel() - 1, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k, ORDERS[order],
+                            ctypes.byref(opt), out.data_ptr(), capacity, ctypes.byref(written), ctypes.byref(total))
+    else:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        out = np.empty((max(capacity, 1), k), dtype=np.int32)
+        rc = L.kclique_list(len(rp) - 1, rp.ctypes.data, ci.ctypes.data if ci.size else None, k, ORDERS[order],
+                            ctypes.byref(opt), out.ctypes.data, capacity, ctypes.byref(written), ctypes.byref(total))
+    _check(rc, "kclique_list")
+    return out[: written.value], int(total.value)
 
 
 def count_host(row_ptr, col_idx, k: int, order: str = "color") -> int:

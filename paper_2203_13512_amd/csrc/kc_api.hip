@@ -52,6 +52,44 @@ __global__ void k_small_k(int32_t n, const int32_t* __restrict__ rp, int32_t k, 
   pv[v] = k == 1 ? 1ull : (unsigned long long)(rp[v + 1] - rp[v]);
 }
 
+// Listing output for k = 1 (every vertex) and k = 2 (every edge, as (u, v)
+// with u < v; rows of vertex u start at the prefix sum of the higher
+// neighbour counts).
+__global__ void k_emit_k1(int32_t n, kc_emit e) {
+  const int64_t T = n < e.cap ? n : e.cap;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < T; v += (int64_t)gridDim.x * blockDim.x)
+    e.out[v] = (int32_t)v;
+}
+__global__ void k_higher_deg(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t* hd) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / KC_WAVE;
+  if (wave >= n) return;
+  const int32_t u = (int32_t)wave;
+  int32_t c = 0;
+  for (int32_t i = rp[u] + kc_lane(); i < rp[u + 1]; i += KC_WAVE) c += col[i] > u;
+  c = (int32_t)kc_wave_sum_u32((uint32_t)c);
+  if (kc_lane() == 0) hd[u] = c;
+}
+__global__ void k_emit_k2(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const int32_t* __restrict__ off, kc_emit e) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / KC_WAVE;
+  if (wave >= n) return;
+  const int32_t u = (int32_t)wave;
+  int64_t o = off[u];
+  const int32_t b = rp[u], en = rp[u + 1];
+  for (int32_t base = b; base < en; base += KC_WAVE) {
+    const int32_t i = base + kc_lane();
+    const int32_t v = i < en ? col[i] : -1;
+    const bool take = v > u;
+    const uint64_t m = kc_ballot(take);
+    const int64_t row = o + kc_mbcnt(m);
+    if (take && row < e.cap) {
+      e.out[2 * row] = u;
+      e.out[2 * row + 1] = v;
+    }
+    o += __popcll(m);
+  }
+}
+
 // Timing events of a call, created only when statistics are asked for.
 struct HostEvents {
   hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -80,16 +118,20 @@ struct HostEvents {
 static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                       const kc_options* opt_in, uint64_t* count_out, uint64_t* pv_out,
                       kc_scratch* ext_scr = nullptr, kc_capture* cap = nullptr, size_t* size_out = nullptr,
-                      bool size_pv = false) {
+                      bool size_pv = false, int32_t* list_out = nullptr, int64_t list_cap = 0,
+                      int64_t* written_out = nullptr) {
   kc_options defaults;
   memset(&defaults, 0, sizeof(defaults));
   const kc_options* opt = opt_in ? opt_in : &defaults;
   if (n < 0 || k < 1 || !count_out) return KC_EINVAL;
   if (cap && (!ext_scr || order != KC_ORDER_COLOR || pv_out)) return KC_EUNSUPPORTED;
-  if (order != KC_ORDER_DEGREE && order != KC_ORDER_COLOR) return KC_EINVAL;
+  if (order != KC_ORDER_DEGREE && order != KC_ORDER_COLOR && order != KC_ORDER_CORE) return KC_EINVAL;
+  if (opt->disable & ~(KC_NO_PRECORE | KC_NO_PRELIST | KC_NO_PRUNE)) return KC_EINVAL;
   if (opt->schedule != KC_SCHED_DEGREE && opt->schedule != KC_SCHED_LEARNED) return KC_EINVAL;
   if (n > 0 && !row_ptr) return KC_EINVAL;
   if (opt->workspace && !ext_scr && !size_out && opt->workspace_bytes == 0) return KC_EWORKSPACE;
+  const bool listing = written_out != nullptr;
+  if (listing && (pv_out || cap || opt->vertex_k || list_cap < 0 || (list_cap > 0 && !list_out))) return KC_EINVAL;
   int dev_count = 0;
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return KC_EDEVICE;
   hipStream_t s = (hipStream_t)opt->stream;
@@ -148,6 +190,15 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     else KC_TRY(scr.get(&pv_d, (size_t)n + 1));
     if (n > 0) KC_HIP(hipMemsetAsync(pv_d, 0, sizeof(unsigned long long) * (size_t)n, s));
   }
+  kc_emit em;
+  unsigned long long small_rows = 0;  // rows of the k <= 2 output (host source of a copy)
+  if (listing) {
+    em.cap = list_cap;
+    KC_TRY(scr.get(&em.pos, 2));
+    KC_HIP(hipMemsetAsync(em.pos, 0, sizeof(unsigned long long), s));
+    if (opt->device_ptrs) em.out = list_out;
+    else if (list_cap > 0) KC_TRY(scr.get(&em.out, (size_t)list_cap * (size_t)k));
+  }
   if (n > 0) {
     if (opt->root_count) KC_HIP(hipMemsetAsync(opt->root_count, 0, sizeof(uint64_t) * (size_t)n, s));
     if (opt->root_work) KC_HIP(hipMemsetAsync(opt->root_work, 0, sizeof(uint64_t) * (size_t)n, s));
@@ -177,13 +228,31 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
       k_small_k<<<(n + 255) / 256, 256, 0, s>>>(n, g.rp, k, pv_d);
       KC_HIP(hipGetLastError());
     }
+    if (listing && n > 0 && k <= 2 && list_cap > 0) {
+      if (k == 1) {
+        k_emit_k1<<<1024, 256, 0, s>>>(n, em);
+      } else {
+        int32_t *hd, *off;
+        KC_TRY(scr.get(&hd, (size_t)n + 1));
+        KC_TRY(scr.get(&off, (size_t)n + 1));
+        k_higher_deg<<<(unsigned)(((int64_t)n * KC_WAVE + 255) / 256), 256, 0, s>>>(n, g.rp, g.col, hd);
+        KC_HIP(hipGetLastError());
+        KC_TRY(kc_scan_i32(hd, off, n, nullptr, scr, s));
+        k_emit_k2<<<(unsigned)(((int64_t)n * KC_WAVE + 255) / 256), 256, 0, s>>>(n, g.rp, g.col, off, em);
+      }
+      KC_HIP(hipGetLastError());
+    }
+    if (listing) {
+      small_rows = k <= 2 ? (unsigned long long)total : 0ull;
+      KC_HIP(hipMemcpyAsync(em.pos, &small_rows, sizeof(small_rows), hipMemcpyHostToDevice, s));
+    }
     KC_TRY(ev.record(1, s));
     KC_TRY(ev.record(2, s));
   } else {
     if (k > KC_KMAX_LIMIT) return KC_EUNSUPPORTED;
     kc_prep_out prep;
     KC_TRY(kc_preprocess(g, k, vk, order, prelist_d, pv_d, (unsigned long long*)opt->root_count, flags, &prep,
-                         scr, s));
+                         scr, s, listing ? &em : nullptr, opt->disable));
     KC_TRY(ev.record(1, s));
     int32_t *roots, *rinfo;
     KC_TRY(scr.get(&roots, (size_t)n + 1));
@@ -216,9 +285,10 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     c.stats = stats;
     c.capture = cap;
     c.size_only = size_out != nullptr;
+    c.emit = listing ? &em : nullptr;
     KC_TRY(ev.record(2, s));
-    if (order == KC_ORDER_DEGREE) KC_TRY(kc_list_sdegree(c, scr, s));
-    else KC_TRY(kc_list_bitcol(c, scr, s));
+    if (order == KC_ORDER_COLOR) KC_TRY(kc_list_bitcol(c, scr, s));
+    else KC_TRY(kc_list_sdegree(c, scr, s));
     if (size_out) {
       KC_HIP(hipStreamSynchronize(s));
       *size_out = scr.need;
@@ -252,7 +322,18 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   KC_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
   if (pv_out && !opt->device_ptrs && n > 0)
     KC_HIP(hipMemcpyAsync(pv_out, pv_d, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+  unsigned long long reserved = 0;
+  if (listing) KC_HIP(hipMemcpyAsync(&reserved, em.pos, sizeof(reserved), hipMemcpyDeviceToHost, s));
   KC_HIP(hipStreamSynchronize(s));
+  if (listing) {
+    const int64_t written = (int64_t)(reserved < (unsigned long long)list_cap ? reserved : (unsigned long long)list_cap);
+    *written_out = written;
+    if (!opt->device_ptrs && written > 0) {
+      KC_HIP(hipMemcpyAsync(list_out, em.out, sizeof(int32_t) * (size_t)written * (size_t)k, hipMemcpyDeviceToHost,
+                            s));
+      KC_HIP(hipStreamSynchronize(s));
+    }
+  }
   if (hflags & KC_FLAG_OVERFLOW) return KC_EOVERFLOW;
   if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
   if (k > 2 && (k <= n || vk)) {
@@ -278,6 +359,22 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
 extern "C" int kclique_count_ex(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                                 const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out) {
   return count_impl(n, row_ptr, col_idx, k, order, opt, count_out, per_vertex_out);
+}
+
+extern "C" int kclique_list(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                            const kc_options* opt, int32_t* cliques_out, int64_t capacity, int64_t* written_out,
+                            uint64_t* count_out) {
+  if (!written_out || !count_out) return KC_EINVAL;
+  *written_out = 0;
+  kc_options o;
+  if (opt) o = *opt;
+  else memset(&o, 0, sizeof(o));
+  // the schedule and the per-root logs do not apply to the output pass
+  o.root_work = nullptr;
+  o.root_isect = nullptr;
+  o.root_features = nullptr;
+  return count_impl(n, row_ptr, col_idx, k, order, &o, count_out, nullptr, nullptr, nullptr, nullptr, false,
+                    cliques_out, capacity, written_out);
 }
 
 extern "C" int kclique_workspace_size(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k,

@@ -319,6 +319,7 @@ struct ListArgs {
   unsigned long long* root_count;    // per-root attribution (nullable)
   int cmax;   // re-encode sets of at most cmax members (0 = never)
   int clev;   // ... at nodes of level >= clev
+  int noprune;  // ablation: every position counts as color >= any level (no color prune)
   unsigned long long* count;
   unsigned long long* pv;
   unsigned long long* counters;  // nodes, isect, work, wave-wide joins, joins on re-encoded rows
@@ -1183,7 +1184,7 @@ __global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
           if (PV) Bil[w * SP + p] = in ? a.Bin[bo + (int64_t)w * Sr + p] : 0u;
         }
       for (int p = tid; p < S; p += 64 * NW) {
-        col[p] = p < s ? (uint32_t)a.color[po + p] : 0xffffu;
+        col[p] = p < s ? (a.noprune ? 0xfffeu : (uint32_t)a.color[po + p]) : 0xffffu;
         if (PV) cnt[p] = 0;
       }
       if (tid == 0) {
@@ -1265,6 +1266,152 @@ __global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
       __syncthreads();
     }
   }
+}
+
+// ============================================================== listing output
+// Emission of every clique (kclique_list): one wave per root, BitColList
+// (Alg. 6) depth-first on the root's bitmaps in LDS with the same pruning
+// (candidates of color >= l only, a child entered when it has >= l-1
+// members).  At l = 2 the node's candidate v and each w of B(v) & C give the
+// clique R + {v, w} (the emit step of Alg. 6): the wave reserves one row per
+// clique with one atomic, lane i writes the rows of the members in word i.
+struct EmitArgs {
+  const int32_t* roots;
+  RootInfo ri;
+  const uint32_t* B;
+  const int32_t* perm;
+  const uint16_t* color;
+  int k;
+  const int32_t* vk;
+  kc_emit e;
+  unsigned long long* count;
+  int* flags;
+};
+
+template <int W>
+struct EmitLayout {
+  static constexpr int S = 32 * W;
+  static constexpr int SP = S + 1;
+  static constexpr int oStk = W * SP;                       // candidate sets, [KMAX][W]
+  static constexpr int oGid = oStk + KC_KMAX * W;            // position -> vertex id, [S]
+  static constexpr int oFirst = oGid + S;                    // first position of each color, [KMAX+2]
+  static constexpr int oChosen = oFirst + KC_KMAX + 2;       // vertex chosen at each level, [KMAX]
+  static constexpr int oCur = oChosen + KC_KMAX;             // next position to try, [KMAX]
+  static constexpr int words = oCur + KC_KMAX;
+};
+
+template <int W>
+__global__ __launch_bounds__(64) void k_bitcol_emit(EmitArgs a, const int32_t* __restrict__ list, int32_t nlist) {
+  using LY = EmitLayout<W>;
+  constexpr int S = LY::S, SP = LY::SP;
+  extern __shared__ uint32_t lds[];
+  uint32_t* Bl = lds;
+  uint32_t* stk = lds + LY::oStk;
+  int32_t* gid = (int32_t*)(lds + LY::oGid);
+  int32_t* firstpos = (int32_t*)(lds + LY::oFirst);
+  int32_t* chosen = (int32_t*)(lds + LY::oChosen);
+  int32_t* cur = (int32_t*)(lds + LY::oCur);
+  const int lane = threadIdx.x;
+  uint64_t found = 0;
+  for (int32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+    const int32_t r = list[li];
+    const int32_t u = a.roots[r];
+    const int32_t s = a.ri.s[r];
+    const int Wc = d_wclass_words(a.ri.cls[r]);
+    const int Sr = 32 * Wc;
+    const int64_t bo = a.ri.boff[r], po = a.ri.poff[r];
+    const int k = kc_vk(a.vk, u, a.k);
+    for (int w = 0; w < W; ++w)
+      for (int p = lane; p < S; p += 64) Bl[w * SP + p] = (w < Wc && p < Sr) ? a.B[bo + (int64_t)w * Sr + p] : 0u;
+    for (int p = lane; p < S; p += 64) gid[p] = p < s ? a.perm[po + p] : -1;
+    if (lane <= k + 1 && lane <= KC_KMAX + 1) {
+      int lo = 0, hi = s;  // colors ascend with position
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)a.color[po + mid] < lane) lo = mid + 1; else hi = mid;
+      }
+      firstpos[lane] = lo;
+    }
+    const int L0 = k - 1;
+    if (lane < W) {
+      const int lo = lane * 32;
+      stk[lane] = lo >= s ? 0u : (s - lo >= 32 ? ~0u : ((1u << (s - lo)) - 1u));
+    }
+    __syncthreads();
+    if (lane == 0) cur[0] = firstpos[L0];
+    kc_wave_lds_sync();
+    int d = 0;
+    for (;;) {
+      const int l = L0 - d;
+      const uint32_t mw = lane < W ? stk[d * W + lane] : 0u;
+      const int x = split_next<W>(mw, cur[d], lane);
+      if (x < 0) {
+        if (d == 0) break;
+        d--;
+        continue;
+      }
+      if (lane == 0) cur[d] = x + 1;
+      kc_wave_lds_sync();
+      const uint32_t nw = lane < W ? (Bl[lane * SP + x] & mw) : 0u;
+      const int pc = __popc(nw);
+      if (l == 2) {
+        // exclusive prefix of the members over the words, then the rows
+        int incl = pc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += y;
+        }
+        const int t = __shfl(incl, 63, 64);
+        if (t == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(a.e.pos, (unsigned long long)t);
+        base = (unsigned long long)__shfl((long long)base, 0, 64);
+        found += t;
+        uint32_t m = nw;
+        unsigned long long row = base + (unsigned long long)(incl - pc);
+        const int32_t vx = gid[x];
+        while (m) {
+          const int b = __ffs(m) - 1;
+          m &= m - 1;
+          if (row < (unsigned long long)a.e.cap) {
+            int32_t* o = a.e.out + (int64_t)row * a.k;
+            o[0] = u;
+            for (int i = 0; i < d; ++i) o[1 + i] = chosen[i];
+            o[1 + d] = vx;
+            o[2 + d] = gid[lane * 32 + b];
+          }
+          row++;
+        }
+      } else if ((int)split_popc(nw) >= l - 1) {
+        if (lane == 0) {
+          chosen[d] = gid[x];
+          cur[d + 1] = firstpos[l - 1];
+        }
+        if (lane < W) stk[(d + 1) * W + lane] = nw;
+        kc_wave_lds_sync();
+        d++;
+      }
+    }
+    __syncthreads();
+  }
+  const uint64_t tot = kc_wave_sum_u64(lane == 0 ? found : 0);
+  if (lane == 0 && tot) kc_add_checked(a.count, tot, a.flags);
+}
+
+template <int W>
+static int launch_emit(const EmitArgs& a, const int32_t* list, int32_t nlist, hipStream_t st) {
+  const size_t bytes = 4 * (size_t)EmitLayout<W>::words;
+  auto fn = k_bitcol_emit<W>;
+  KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  int per_cu = 0;
+  KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, bytes));
+  int64_t grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * kc_device_cus() * 2;
+  if (grid > nlist) grid = nlist;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), bytes, st, a, list, nlist);
+  KC_HIP(hipGetLastError());
+  return KC_OK;
 }
 
 // ============================================================== scheduling
@@ -1353,6 +1500,7 @@ struct SplitArgs {
   const float* logw;
   int k;
   const int32_t* vk;
+  int noprune;
   uint64_t* tasks;
   int32_t* task_bin;
   unsigned long long* ntasks;
@@ -1377,7 +1525,7 @@ __global__ __launch_bounds__(64) void k_bitcol_split(SplitArgs a, const int32_t*
     uint64_t nodes = 1, isect = 0;  // the top call
     for (int p0 = 0; p0 < s; p0 += 64) {
       const int v1 = p0 + lane;
-      bool ok1 = v1 < s && (int)colr[v1] >= k - 1;
+      bool ok1 = v1 < s && (a.noprune || (int)colr[v1] >= k - 1);
       int pc1 = 0;
       if (ok1)
         for (int w = 0; w < Wc; ++w) pc1 += __popc(Br[w * Sr + v1]);
@@ -1410,7 +1558,7 @@ __global__ __launch_bounds__(64) void k_bitcol_split(SplitArgs a, const int32_t*
           for (int q0 = 0; q0 < s; q0 += 64) {
             const int v2 = q0 + lane;
             bool mem = v2 < s && ((c1[(v2 >> 5) & 31] >> (v2 & 31)) & 1u);
-            bool ok2 = mem && (int)colr[v2] >= k - 2;
+            bool ok2 = mem && (a.noprune || (int)colr[v2] >= k - 2);
             int pc2 = 0;
             if (ok2)
               for (int w = 0; w < Wc; ++w) pc2 += __popc(Br[w * Sr + v2] & c1[w]);
@@ -1730,6 +1878,36 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     KC_HIP(hipGetLastError());
   }
   KC_TRY(ev_stage.stop(st));
+  if (c.emit) {
+    // listing output: every root in one launch per word class, no schedule
+    EmitArgs ea;
+    ea.roots = c.roots;
+    ea.ri = ri;
+    ea.B = B;
+    ea.perm = perm;
+    ea.color = color;
+    ea.k = c.k;
+    ea.vk = c.vk;
+    ea.e = *c.emit;
+    ea.count = c.count;
+    ea.flags = c.flags;
+    for (int cl = 0; cl < KC_NCLASS; ++cl) {
+      const int32_t cnt = hoff[cl + 1] - hoff[cl];
+      if (cnt <= 0 || c.size_only) continue;
+      const int32_t* lst = byclass + hoff[cl];
+      switch (cl) {
+        case 0: KC_TRY(launch_emit<1>(ea, lst, cnt, st)); break;
+        case 1: KC_TRY(launch_emit<2>(ea, lst, cnt, st)); break;
+        case 2: KC_TRY(launch_emit<4>(ea, lst, cnt, st)); break;
+        case 3: KC_TRY(launch_emit<8>(ea, lst, cnt, st)); break;
+        case 4: KC_TRY(launch_emit<12>(ea, lst, cnt, st)); break;
+        case 5: KC_TRY(launch_emit<16>(ea, lst, cnt, st)); break;
+        case 6: KC_TRY(launch_emit<24>(ea, lst, cnt, st)); break;
+        case 7: KC_TRY(launch_emit<32>(ea, lst, cnt, st)); break;
+      }
+    }
+    return KC_OK;
+  }
   if (c.root_features) {
     k_scatter_features<<<(R * 4 + 255) / 256, 256, 0, st>>>(R, c.roots, feat, c.root_features);
     KC_HIP(hipGetLastError());
@@ -1819,6 +1997,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   sp.logw = logw;
   sp.k = c.k;
   sp.vk = c.vk;
+  sp.noprune = opt && (opt->disable & KC_NO_PRUNE) ? 1 : 0;
   sp.root_isect = c.root_isect;
   sp.root_work = c.root_work;
   sp.counters = c.counters;
@@ -1897,6 +2076,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
       la.cmax = want == 0 ? cap : (want < 0 ? 0 : (want > cap ? cap : want));
     }
     la.clev = opt && opt->compress_level > 0 ? opt->compress_level : 4;
+    la.noprune = opt && (opt->disable & KC_NO_PRUNE) ? 1 : 0;
     la.count = c.count;
     la.pv = c.pv;
     la.counters = cls_ctr + KC_NCTR * cl;

@@ -148,12 +148,21 @@ struct kc_scratch {
 int kc_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev, kc_scratch& scr, hipStream_t s);
 int kc_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_dev, kc_scratch& scr, hipStream_t s);
 
+// Listing output: rows of k vertex ids written to `out` (device, row-major),
+// at most `cap` of them; `pos` (device) counts the rows reserved so far --
+// rows at or beyond `cap` are counted but not written.
+struct kc_emit {
+  int32_t* out = nullptr;
+  int64_t cap = 0;
+  unsigned long long* pos = nullptr;
+};
+
 // Preprocessing (kc_prep.hip).
 struct kc_prep_out {
   uint8_t* removed;   // [n] 1 = removed by Pre-Core or Pre-List
   int32_t* deg;       // [n] live degree after Pre-Core
   int32_t* key;       // [n] order key (degree or peel round)
-  int32_t* core;      // [n] core number (COLOR order), else null
+  int32_t* core;      // [n] core number (degeneracy orders), else null
   int32_t* drp;       // [n+1] DAG row pointers
   int32_t* dcol;      // DAG columns (ascending id per row)
   int64_t dnnz;
@@ -162,7 +171,8 @@ struct kc_prep_out {
 int kc_validate_graph(const kc_dev_graph& g, int* flags_dev, hipStream_t s);
 int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
                   unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
-                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s);
+                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s, const kc_emit* emit = nullptr,
+                  int32_t disable = 0);
 
 // Listing (kc_sdegree.hip, kc_bitcol.hip).
 struct kc_list_ctx {
@@ -188,6 +198,7 @@ struct kc_list_ctx {
   kc_stats* stats;
   struct kc_capture* capture;  // non-null: prepare only, hand the listing phase over
   bool size_only;              // stop before the listing launches (workspace size query)
+  const kc_emit* emit;         // non-null: write every clique listed (no schedule, no per-vertex output)
 };
 
 // A prepared call's listing phase, to be captured into a HIP graph and

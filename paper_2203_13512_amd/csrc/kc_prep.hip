@@ -190,12 +190,12 @@ int kc_validate_graph(const kc_dev_graph& g, int* flags_dev, hipStream_t s) {
 
 // ---------------------------------------------------------------- Pre-Core
 __global__ void k_precore_init(int32_t n, const int32_t* __restrict__ rp, int32_t km1, const int32_t* vk,
-                               int32_t* deg, uint8_t* removed, int32_t* F, int32_t* fcount) {
+                               int32_t* deg, uint8_t* removed, int32_t* F, int32_t* fcount, bool skip) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   int32_t d = rp[v + 1] - rp[v];
   deg[v] = d;
-  bool rm = d < kc_vk(vk, v, km1 + 1) - 1;
+  bool rm = !skip && d < kc_vk(vk, v, km1 + 1) - 1;
   removed[v] = rm ? 1 : 0;
   if (rm) F[atomicAdd(fcount, 1)] = v;
 }
@@ -298,6 +298,72 @@ __global__ void k_prelist_remove(int32_t n, int32_t k, const int32_t* vk, uint8_
       return;
     }
     kc_add_checked(&pv[v], c, flags);
+  }
+}
+
+// ------------------------------------------------- Pre-List output
+// Listing mode: a clique component reports each of its C(n_c, k) k-subsets
+// (Alg. 4).  Its members are gathered into one list per component; the
+// components' subset counts (capped at the output capacity) are prefix-summed
+// into row offsets, and row t of component c is the t-th k-subset of its
+// member list in the combinatorial number system: the largest a_k with
+// C(a_k, k) <= t, then the largest a_{k-1} < a_k with C(a_{k-1}, k-1) <=
+// t - C(a_k, k), and so on.
+__global__ void k_pl_sizes(int32_t n, int32_t k, const int32_t* vk, const uint8_t* __restrict__ removed,
+                           const int32_t* __restrict__ parent, const uint8_t* __restrict__ is_clique,
+                           const int32_t* __restrict__ comp_n, int64_t cap, int32_t* msz, int64_t* tsz) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const bool root = !removed[v] && parent[v] == v && is_clique[v];
+  uint64_t c = 0;
+  if (root && !kc_binom((uint64_t)comp_n[v], (uint64_t)kc_vk(vk, v, k), &c)) c = ~0ull;
+  msz[v] = root ? comp_n[v] : 0;
+  tsz[v] = root ? (int64_t)(c < (uint64_t)cap ? c : (uint64_t)cap) : 0;
+}
+
+__global__ void k_pl_members(int32_t n, const uint8_t* __restrict__ removed, const int32_t* __restrict__ parent,
+                             const uint8_t* __restrict__ is_clique, const int32_t* __restrict__ moff, int32_t* fill,
+                             int32_t* members) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || removed[v]) return;
+  const int32_t r = parent[v];
+  if (!is_clique[r]) return;
+  members[moff[r] + atomicAdd(&fill[r], 1)] = v;
+}
+
+// true when C(c, j) <= x (a value past 64 bits is larger than any x)
+__device__ __forceinline__ bool binom_le(uint64_t c, uint64_t j, uint64_t x, uint64_t* val) {
+  return kc_binom(c, j, val) && *val <= x;
+}
+
+__global__ void k_pl_emit(int32_t n, int32_t k, const int32_t* vk, const int64_t* __restrict__ toff,
+                          const int32_t* __restrict__ moff, const int32_t* __restrict__ comp_n,
+                          const int32_t* __restrict__ members, const int64_t* __restrict__ total, kc_emit e) {
+  const int64_t T = *total < e.cap ? *total : e.cap;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x) {
+    // the component whose row range holds t: the last vertex with offset <= t
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (toff[mid] <= t) lo = mid + 1; else hi = mid;
+    }
+    const int32_t c = lo - 1;
+    uint64_t x = (uint64_t)(t - toff[c]);
+    const int kc = kc_vk(vk, c, k);
+    int32_t top = comp_n[c] - 1;
+    int32_t* row = e.out + t * (int64_t)k;
+    for (int j = kc; j >= 1; --j) {
+      int32_t a = j - 1, b = top;
+      uint64_t val = 0;
+      while (a < b) {  // largest element a with C(a, j) <= x
+        const int32_t mid = a + ((b - a + 1) >> 1);
+        if (binom_le((uint64_t)mid, (uint64_t)j, x, &val)) a = mid; else b = mid - 1;
+      }
+      kc_binom((uint64_t)a, (uint64_t)j, &val);
+      x -= val;
+      row[kc - j] = members[moff[c] + a];
+      top = a - 1;
+    }
   }
 }
 
@@ -445,7 +511,8 @@ static int read_i32(const int32_t* dev, int32_t* host, hipStream_t s) {
 
 int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
                   unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
-                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s) {
+                  int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s, const kc_emit* emit,
+                  int32_t disable) {
   const int32_t n = g.n;
   const int32_t km1 = k - 1;
   memset(out, 0, sizeof(*out));
@@ -462,7 +529,8 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
   // ---- Pre-Core (Alg. 3)
   KC_HIP(hipMemsetAsync(counters, 0, 8 * sizeof(int32_t), s));
   if (n > 0) {
-    k_precore_init<<<grid_for(n), 256, 0, s>>>(n, g.rp, km1, vk, out->deg, out->removed, F0, counters);
+    k_precore_init<<<grid_for(n), 256, 0, s>>>(n, g.rp, km1, vk, out->deg, out->removed, F0, counters,
+                                               (disable & KC_NO_PRECORE) != 0);
     KC_HIP(hipGetLastError());
   }
   KC_TRY(read_i32(counters, hcnt, s));
@@ -478,7 +546,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
   }
 
   // ---- Pre-List (Alg. 4)
-  {
+  if (!(disable & KC_NO_PRELIST)) {
     int32_t *parent, *comp_n;
     unsigned long long* comp_dsum;
     uint8_t* is_clique;
@@ -494,6 +562,34 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
       k_uf_stats<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, out->deg, comp_n, comp_dsum);
       k_prelist_roots<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, comp_dsum, is_clique,
                                                    prelist_count_dev, root_count, flags_dev);
+      KC_HIP(hipGetLastError());
+    }
+    if (emit) {
+      // report the clique components' k-subsets; the listing's rows follow
+      int32_t *msz, *moff, *fill, *members;
+      int64_t *tsz, *toff, *ttot;
+      KC_TRY(scr.get(&msz, (size_t)n + 1));
+      KC_TRY(scr.get(&moff, (size_t)n + 1));
+      KC_TRY(scr.get(&fill, (size_t)n + 1));
+      KC_TRY(scr.get(&members, (size_t)n + 1));
+      KC_TRY(scr.get(&tsz, (size_t)n + 1));
+      KC_TRY(scr.get(&toff, (size_t)n + 1));
+      KC_TRY(scr.get(&ttot, 2));
+      if (n > 0) {
+        k_pl_sizes<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, is_clique, comp_n, emit->cap, msz, tsz);
+        KC_HIP(hipGetLastError());
+      }
+      KC_TRY(kc_scan_i32(msz, moff, n, nullptr, scr, s));
+      KC_TRY(kc_scan_i64(tsz, toff, n, ttot, scr, s));
+      if (n > 0) {
+        KC_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * (size_t)n, s));
+        k_pl_members<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, is_clique, moff, fill, members);
+        k_pl_emit<<<1024, 256, 0, s>>>(n, k, vk, toff, moff, comp_n, members, ttot, *emit);
+        KC_HIP(hipGetLastError());
+      }
+      KC_HIP(hipMemcpyAsync(emit->pos, ttot, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    }
+    if (n > 0) {
       k_prelist_remove<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, is_clique, pv_dev,
                                                     flags_dev);
       KC_HIP(hipGetLastError());
@@ -506,6 +602,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
     // so the Pre-Core degrees of the survivors are unchanged)
     if (n > 0) KC_HIP(hipMemcpyAsync(out->key, out->deg, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
   } else {
+    // degeneracy order (BitCol, and SDegree on the degeneracy order)
     KC_TRY(scr.get(&out->core, (size_t)n + 1));
     int32_t *A0, *A1, *pdeg;
     uint8_t* peeled;

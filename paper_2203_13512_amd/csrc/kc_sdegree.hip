@@ -58,6 +58,8 @@ struct SdArgs {
   uint64_t* root_work;
   uint64_t* root_isect;
   int* flags;
+  kc_emit e;              // listing output (EMIT instances)
+  int noprune;            // ablation: no d+ <= l-2 skip; a child with any member is entered
 };
 
 // Memory of one workgroup (words): list[K][SMAX] | lidx[K][SMAX] (per-vertex)
@@ -75,7 +77,10 @@ __device__ __forceinline__ int sd_lower_bound(const int32_t* a, int lo, int hi, 
   return lo;
 }
 
-template <bool PV>
+// EMIT: write every clique found (the emit step of Alg. 5: R + {x, y} for
+// each hit y of a join at l = 2), rows reserved per 64-entry chunk with one
+// atomic; `chosen` then holds the vertex ids of R.
+template <bool PV, bool EMIT>
 __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   extern __shared__ uint32_t lds[];
   uint32_t* mem = a.gscratch ? a.gscratch + (size_t)blockIdx.x * a.block_words : lds;
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           continue;
         }
         int32_t* C = list + (size_t)d * SM;
-        if (!PV && l == 2) {
+        if (!PV && !EMIT && l == 2) {
           // A level-2 node, lane-parallel: lane i takes candidate C[c + i]
           // (and every 64th after it) and counts |N+(x) ∩ C| on its own,
           // walking N+(x) within [min C, max C] with a moving binary search
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
             const int32_t x = C[idx];
             const int32_t xb = a.drp[x], xe = a.drp[x + 1];
             const int dx = xe - xb;
-            if (dx <= 0) continue;
+            if (dx <= 0 && !a.noprune) continue;
             my_isect++;
             my_work += (uint64_t)sz + (uint64_t)dx;
             int lo = xb, hi = xe;
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
         kc_wave_lds_sync();
         const int32_t xb = a.drp[x], xe = a.drp[x + 1];
         const int dx = xe - xb;
-        if (dx <= l - 2) continue;
+        if (dx <= l - 2 && !a.noprune) continue;
         my_isect += (lane == 0);
         my_work += lane == 0 ? (uint64_t)sz + (uint64_t)dx : 0u;
         // merge join N+(x) with C
@@ -218,6 +223,19 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           const uint64_t mk = kc_ballot(hit);
           if (l == 2) {
             if (PV && hit) atomicAdd(&cnt[lidx[(size_t)d * SM + p]], 1ull);
+            if (EMIT && mk) {
+              unsigned long long base = 0;
+              if (lane == 0) base = atomicAdd(a.e.pos, (unsigned long long)__popcll(mk));
+              base = (unsigned long long)__shfl((long long)base, 0, 64);
+              const unsigned long long row = base + (unsigned long long)kc_mbcnt(mk);
+              if (hit && row < (unsigned long long)a.e.cap) {
+                int32_t* o = a.e.out + (int64_t)row * a.k;
+                o[0] = u;
+                for (int q = 0; q < d; ++q) o[1 + q] = chosen[q];
+                o[1 + d] = x;
+                o[2 + d] = y;
+              }
+            }
           } else if (hit) {
             const int o = m + kc_mbcnt(mk);
             Cn[o] = y;
@@ -235,9 +253,9 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
             if (PV && m) atomicAdd(&cnt[xi], (unsigned long long)m);
           }
           kc_wave_lds_sync();
-        } else if (m > l - 2) {
+        } else if (a.noprune ? m > 0 : m > l - 2) {
           if (lane == 0) {
-            chosen[d] = xi;
+            chosen[d] = EMIT ? x : xi;
             size[d + 1] = m;
             cur[d + 1] = 0;
             tot[d + 1] = 0;
@@ -371,7 +389,9 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     a.flags = c.flags;
     size_t words = sd_words(c.k, a.SMAX, pv);
     size_t bytes = 4 * words;
-    auto fn = pv ? k_sdegree_list<true> : k_sdegree_list<false>;
+    a.e = c.emit ? *c.emit : kc_emit();
+    a.noprune = c.opt && (c.opt->disable & KC_NO_PRUNE) ? 1 : 0;
+    auto fn = pv ? k_sdegree_list<true, false> : (c.emit ? k_sdegree_list<false, true> : k_sdegree_list<false, false>);
     int64_t grid;
     size_t lds_bytes;
     if (bytes <= 64 * 1024) {

@@ -32,7 +32,7 @@ def dev(g):
 
 CASES = [
     ("chunglu", lambda: graphgen.chung_lu(6000, 10.0, 2.1, 500.0, planted=[22, 16], seed=3), (4, 6)),
-    ("minus_edge", lambda: G.complete_minus_edge(300, 5, 9), (5,)),
+    ("minus_edge", lambda: G.complete_minus_edge(90, 5, 9), (5,)),
     ("union", lambda: G.disjoint_union([G.complete(12), graphgen.erdos_renyi(90, 0.35, seed=2)]), (3, 5)),
 ]
 

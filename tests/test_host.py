@@ -37,8 +37,23 @@ def test_autotune_cache_holds_launch_options_only():
     for key, e in autotune.load_cache().items():
         assert set(e["best"]) <= fields, e["best"]
         assert e["order"] in kc.ORDERS and e["k"] >= 3
-        for cand in autotune.SPACE:
-            assert set(cand) <= fields
+    assert set(autotune.GRID) <= fields
+
+
+def test_autotune_coordinate_descent_finds_the_separable_optimum():
+    """On an objective that is a sum over knobs, one sweep of the coordinate
+    descent reaches the grid's minimum; every evaluation is cached."""
+    calls = []
+    pref = {"waves_per_root": 4, "chunk": 16, "compress": 64, "compress_level": 0, "class_streams": 2}
+
+    def cost(c):
+        calls.append(dict(c))
+        return 100.0 + sum(0.0 if c.get(k, 0) == v else 10.0 + abs(c.get(k, 0) - v) for k, v in pref.items())
+
+    best, table = autotune.coordinate_descent(cost, log=lambda *a: None)
+    assert best == {k: v for k, v in pref.items() if v != 0}
+    assert len(calls) == len(table) == len({str(sorted(c.items())) for c in calls})
+    assert min(table.values()) == 100.0
 
 
 def test_saved_scheduler_model_matches_the_network():

@@ -473,3 +473,54 @@ def test_cocktail_party_closed_form(r):
         if k >= 3:
             for method in ("degree", "color"):
                 assert oracle.method_count(rp, ci, k, method)[0] == c
+
+
+def test_listing_matches_brute_force():
+    """The oracle's listing (Sec. 3.1) writes exactly the k-subsets that are
+    cliques, each once, as ascending ids in lexicographic order."""
+    rng = np.random.default_rng(13)
+    for trial in range(40):
+        n = int(rng.integers(1, 13))
+        rp, ci = graphgen.erdos_renyi(n, float(rng.uniform(0.2, 0.95)), seed=int(rng.integers(1 << 30)))
+        adj = [set(int(x) for x in ci[rp[v]:rp[v + 1]]) for v in range(n)]
+        for k in range(1, 7):
+            want = [S for S in itertools.combinations(range(n), k)
+                    if all(b in adj[a] for a, b in itertools.combinations(S, 2))]
+            rows, total = oracle.list_cliques(rp, ci, k)
+            assert total == len(want)
+            assert [tuple(int(x) for x in r) for r in rows] == want
+            if total > 1:  # a bounded buffer keeps the first rows and the full count
+                part, t2 = oracle.list_cliques(rp, ci, k, capacity=total // 2)
+                assert t2 == total and np.array_equal(part, rows[: total // 2])
+    (rp, ci), n = G.paper_example_graph()
+    rows, total = oracle.list_cliques(rp, ci, 4)
+    # Example 1: {v1,v2,v3,v4}, {v1,v2,v4,v6}, {v9,v10,v11,v12} (0-based here)
+    assert total == 3 and [tuple(int(x) for x in r) for r in rows] == [(0, 1, 2, 3), (0, 1, 3, 5), (8, 9, 10, 11)]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ablations_and_orders_reach_the_definition(seed):
+    """SDegree on the degree or the degeneracy order (Sec. 6.2: any order
+    works) and BitCol reach the plain count with or without Pre-Core,
+    Pre-List and pruning (preprocessing and pruning remove only nodes that
+    hold no clique, Sec. 5 and Lemma 3); dropping them never lowers the
+    number of joins; the degeneracy order bounds out-degrees by core numbers."""
+    graphs = [
+        graphgen.chung_lu(2500, 10.0, 2.1, 300.0, planted=[13, 9], seed=seed),
+        G.disjoint_union([G.complete(8), graphgen.erdos_renyi(70, 0.35, seed=seed), G.complete(5)]),
+    ]
+    for rp, ci in graphs:
+        core = oracle.core_numbers(rp, ci)
+        for k in (3, 4, 5):
+            want = oracle.count(rp, ci, k)
+            for method in ("degree", "core", "color"):
+                base = oracle.method_count(rp, ci, k, method)
+                assert base[0] == want
+                for disable in (1, 2, 4, 7):
+                    got = oracle.method_count(rp, ci, k, method, disable=disable)
+                    assert got[0] == want, (method, disable)
+                    if disable & 4:
+                        assert got[2]["isect"].sum() >= base[2]["isect"].sum()
+                if method == "core":
+                    d = base[2]["dplus"]
+                    assert np.all(d <= np.maximum(core, 0))
