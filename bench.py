@@ -51,7 +51,7 @@ MI355X_CUS = 256
 MI355X_CLOCK_HZ = 2.4e9
 # int32 VALU: 4 SIMDs x 16 lanes per CU per clock (v_and_b32, v_bcnt_u32_b32)
 INT32_VALU_PEAK_TOPS = MI355X_CUS * 4 * 16 * MI355X_CLOCK_HZ / 1e12
-WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32]
+WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
 
 # HBM bytes of the dominant listing launch (16-word bitmaps, learned schedule,
 # 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE

@@ -50,7 +50,7 @@ typedef enum {
   KC_ENOMEM = -2,        /* device allocation failed */
   KC_EOVERFLOW = -3,     /* a count does not fit in 64 bits (e.g. C(201,20)) */
   KC_EDEVICE = -4,       /* a HIP runtime call failed or no device */
-  KC_EUNSUPPORTED = -5,  /* a local subgraph exceeds the supported size */
+  KC_EUNSUPPORTED = -5,  /* a local subgraph exceeds the supported size (2048 local vertices) */
   KC_EWORKSPACE = -6     /* the caller's workspace is smaller than the call needs */
 } kc_status;
 
@@ -97,10 +97,11 @@ typedef struct {
   uint64_t stage_bytes;   /* BitCol: algorithmic bytes read while staging: 4*(d+_u + sum of d+_v) */
   uint64_t isect_wide;    /* BitCol: of `isect`, BitJoins done as one whole-wave step on full-width bitmaps */
   uint64_t isect_compressed; /* BitCol: of `isect`, BitJoins on re-encoded 64-bit rows (see `compress`) */
-  /* per listing launch (BitCol: bitmap word class 1,2,4,8,12,16,24,32; SDegree: candidate-list class) */
-  double class_ms[8];     /* device time of that class's persistent listing kernel */
-  uint64_t class_work[8]; /* its work, as `work` above */
-  int64_t class_tasks[8]; /* its queue length */
+  /* per listing launch (BitCol: bitmap word class 1,2,4,8,12,16,24,32,48,64; SDegree: candidate-list
+   * class of at most 64, 256, 1024, 4096, 16384, 65536 entries) */
+  double class_ms[10];     /* device time of that class's persistent listing kernel */
+  uint64_t class_work[10]; /* its work, as `work` above */
+  int64_t class_tasks[10]; /* its queue length */
 } kc_stats;
 
 typedef struct {

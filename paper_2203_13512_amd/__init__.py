@@ -44,8 +44,8 @@ class Stats(ctypes.Structure):
         ("max_core", ctypes.c_int32), ("prelist_count", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
         ("isect", ctypes.c_uint64), ("work", ctypes.c_uint64), ("staged_words", ctypes.c_uint64),
         ("stage_bytes", ctypes.c_uint64), ("isect_wide", ctypes.c_uint64), ("isect_compressed", ctypes.c_uint64),
-        ("class_ms", ctypes.c_double * 8), ("class_work", ctypes.c_uint64 * 8),
-        ("class_tasks", ctypes.c_int64 * 8),
+        ("class_ms", ctypes.c_double * 10), ("class_work", ctypes.c_uint64 * 10),
+        ("class_tasks", ctypes.c_int64 * 10),
     ]
 
     def as_dict(self):

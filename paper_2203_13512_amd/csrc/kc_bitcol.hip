@@ -44,8 +44,12 @@
 
 #include "kc_internal.h"
 
-#define KC_NCLASS 8
-static const int kWClass[KC_NCLASS] = {1, 2, 4, 8, 12, 16, 24, 32};
+#define KC_NCLASS 10
+static const int kWClass[KC_NCLASS] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
+// The widest classes keep their bitmaps in device memory while listing
+// (ListLayout GB): 48 and 64 words always, 24 and 32 words with per-vertex
+// output; their staging builds the local adjacency matrix in device memory.
+static inline bool class_in_device_memory(int cls, bool pv) { return cls >= 8 || (pv && cls >= 6); }
 
 static inline int wclass_of(int s) {
   int w = (s + 31) / 32;
@@ -63,10 +67,12 @@ __device__ __forceinline__ int d_wclass_of(int s) {
   if (w <= 16) return 5;
   if (w <= 24) return 6;
   if (w <= 32) return 7;
+  if (w <= 48) return 8;
+  if (w <= 64) return 9;
   return -1;
 }
 __device__ __forceinline__ int d_wclass_words(int c) {
-  const int t[KC_NCLASS] = {1, 2, 4, 8, 12, 16, 24, 32};
+  const int t[KC_NCLASS] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
   return t[c];
 }
 
@@ -113,14 +119,25 @@ __device__ __forceinline__ int lds_upper_bound(const int32_t* a, int n, int32_t 
 // Dynamic LDS layout for a stage workgroup with class words WM (S = 32*WM):
 //   ids[S] i32 | off[S+1] i32 | deg[S] i32 | order[S] i32 | color[S] i32 |
 //   pos[S] i32 | used[WM+2] u32 | M1[WM*S] u32 | M2[WM*S] u32 (per-vertex)
-static size_t stage_lds_bytes(int WM, bool pv) {
+// With `mat` (device memory, WM*S words per matrix and workgroup) the two
+// matrices live there instead of in LDS.
+static size_t stage_lds_bytes(int WM, bool pv, bool mat_in_lds = true) {
   size_t S = 32 * (size_t)WM;
-  return 4 * (S + S + 1 + S + S + S + S + WM + 2) + 4 * (size_t)WM * S * (pv ? 2 : 1) + 64;
+  return 4 * (S + S + 1 + S + S + S + S + WM + 2) + (mat_in_lds ? 4 * (size_t)WM * S * (pv ? 2 : 1) : 0) + 64;
+}
+
+// Barrier of a staging workgroup.  With the matrices in device memory the
+// bit sets are built by atomics in L2, so the barrier is followed by an
+// acquire at device scope: later loads do not hit stale lines of the CU's
+// vector cache.
+__device__ __forceinline__ void stage_sync(const uint32_t* mat) {
+  __syncthreads();
+  if (mat) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <bool PV>
 __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t* __restrict__ list, int32_t nlist,
-                                                     int WM) {
+                                                     int WM, uint32_t* mat) {
   extern __shared__ uint32_t lds[];
   const int S = 32 * WM;
   int32_t* ids = (int32_t*)lds;
@@ -130,7 +147,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
   int32_t* color = order + S;
   int32_t* pos = color + S;
   uint32_t* used = (uint32_t*)(pos + S);
-  uint32_t* M1 = used + WM + 2;
+  uint32_t* M1 = mat ? mat + (size_t)blockIdx.x * (PV ? 2 : 1) * WM * S : used + WM + 2;
   uint32_t* M2 = M1 + (size_t)WM * S;
   const int lane = threadIdx.x;
 
@@ -154,7 +171,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       M1[i] = 0;
       if (PV) M2[i] = 0;
     }
-    __syncthreads();
+    stage_sync(mat);
     // off = exclusive prefix of deg over i < s (wave scan in chunks of 64)
     {
       int carry = 0;
@@ -172,7 +189,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       }
       if (lane == 0) off[s] = carry;
     }
-    __syncthreads();
+    stage_sync(mat);
     const int32_t T = off[s];
     // pass 1: undirected adjacency of G_u in local (id) order
     unsigned edges = 0;
@@ -192,14 +209,14 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       }
       edges += (unsigned)__popcll(kc_ballot(hit));
     }
-    __syncthreads();
+    stage_sync(mat);
     // local degrees
     for (int i = lane; i < s; i += 64) {
       int d = 0;
       for (int w = 0; w < Wc; ++w) d += __popc(M1[w * S + i]);
       deg[i] = d;
     }
-    __syncthreads();
+    stage_sync(mat);
     // coloring order: degree descending, then id (= local index) ascending
     for (int i = lane; i < s; i += 64) {
       int di = deg[i], rk = 0;
@@ -209,21 +226,21 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       }
       order[rk] = i;
     }
-    __syncthreads();
+    stage_sync(mat);
     // greedy coloring, one vertex at a time
     const int Wu = (s + 1 + 31) / 32;
     int maxc = 0;
     for (int t = 0; t < s; ++t) {
       const int v = order[t];
       for (int w = lane; w < Wu; w += 64) used[w] = 0;
-      __syncthreads();
+      stage_sync(mat);
       for (int j = lane; j < s; j += 64) {
         if ((M1[(j >> 5) * S + v] >> (j & 31)) & 1u) {
           int c = color[j];
           if (c > 0) atomicOr(&used[c >> 5], 1u << (c & 31));
         }
       }
-      __syncthreads();
+      stage_sync(mat);
       int found = 0x7fffffff;
       for (int w0 = 0; w0 < Wu; w0 += 64) {
         int w = w0 + lane;
@@ -239,7 +256,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       }
       if (lane == 0) color[v] = found;
       maxc = found > maxc ? found : maxc;
-      __syncthreads();
+      stage_sync(mat);
     }
     // positions sorted by (color, local index)
     for (int i = lane; i < s; i += 64) {
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       order[p] = i;  // inverse permutation
     }
     for (int i = lane; i < WM * S; i += 64) M1[i] = 0;
-    __syncthreads();
+    stage_sync(mat);
     // pass 2: encoded bitmaps in color order
     for (int32_t t0 = 0; t0 < T; t0 += 64) {
       int32_t t = t0 + lane;
@@ -270,7 +287,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
         }
       }
     }
-    __syncthreads();
+    stage_sync(mat);
     // write out (column-major, Sr positions per word row)
     const int64_t bo = a.ri.boff[r];
     for (int w = 0; w < Wc; ++w)
@@ -298,7 +315,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
       }
       atomicAdd(a.stage_bytes, (unsigned long long)(4ull * ((uint64_t)s + (uint64_t)T)));
     }
-    __syncthreads();
+    stage_sync(mat);
   }
 }
 
@@ -337,15 +354,19 @@ struct ListArgs {
 // time: the candidate list of a level-3 node, or a re-encoded node.
 #define KC_KMAX 32
 
-template <int W, int NW, bool PV, bool COMP>
+// GB: the root's bitmaps are read in place from device memory (the staged
+// column-major block, row stride S) instead of being copied into LDS -- the
+// layout of local subgraphs too large for LDS (48 and 64 words, and the
+// per-vertex classes above 16 words, whose in-neighbour bitmaps double it).
+template <int W, int NW, bool PV, bool COMP, bool GB = false>
 struct ListLayout {
   static constexpr int S = 32 * W;
-  static constexpr int SP = S + 1;  // LDS row stride (bank-conflict free)
+  static constexpr int SP = GB ? S : S + 1;  // row stride (in LDS, S + 1 keeps accesses bank-conflict free)
   static constexpr int a2(int x) { return (x + 1) & ~1; }
   static constexpr int a4(int x) { return (x + 3) & ~3; }
   static constexpr int oB = 0;
-  static constexpr int oBin = oB + W * SP;
-  static constexpr int oCol = oBin + (PV ? W * SP : 0);
+  static constexpr int oBin = oB + (GB ? 0 : W * SP);
+  static constexpr int oCol = oBin + (PV && !GB ? W * SP : 0);
   static constexpr int oFirst = oCol + S;
   static constexpr int oC0 = oFirst + KC_KMAX + 2;
   static constexpr int oSh = a2(oC0 + W);
@@ -389,11 +410,10 @@ __device__ __forceinline__ int split_next(uint32_t w, int from, int lane) {
 
 // Level-2 node with set C (lane-split word in `cw`): returns the node's leaf
 // count (wave-uniform) and adds the BitJoins performed to `joins`.
-template <int W, bool PV>
+template <int W, bool PV, int SP>
 __device__ __forceinline__ uint64_t leaf_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
                                               int s, int first2, uint32_t cw, int lane, uint64_t& joins,
                                               unsigned long long* cnt, int chunk0 = 0, int chunk_step = 1) {
-  constexpr int SP = 32 * W + 1;
   // highest nonzero word bounds the scan
   int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
   if (hiw < 0) return 0;
@@ -441,12 +461,11 @@ __device__ __forceinline__ uint64_t leaf_eval(const uint32_t* __restrict__ Bl, c
 // words up to w's own word are read).  This is BitColList at l = 3 and l = 2
 // with the same pruning and join count, without wave-wide steps per node.
 // Returns this lane's share of the node's leaves; joins/nodes are per lane.
-template <int W, bool PV>
+template <int W, bool PV, int SP>
 __device__ __forceinline__ uint64_t level3_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
                                                 int s, int first2, int first3, uint32_t cw, int lane,
                                                 uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes,
                                                 unsigned long long* cnt, int part, int nparts) {
-  constexpr int SP = 32 * W + 1;
   const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
   if (hiw < 0) return 0;
   uint32_t c[W];
@@ -782,12 +801,11 @@ __device__ __forceinline__ void wdfs2(CQueue2& Q, const uint64_t* __restrict__ c
 // child of a wide node) and unrolls levels 4 and 5 only: every further
 // inlined copy of the unrolled levels adds to the register footprint of the
 // whole listing kernel.
-template <int W>
+template <int W, int SP>
 __device__ __forceinline__ uint64_t compressed_eval2(const uint32_t* __restrict__ Bl,
                                                      const uint32_t* __restrict__ col, int s, int l, uint32_t cw,
                                                      int lane, uint32_t* __restrict__ ureg, uint64_t& joins,
                                                      uint64_t& nodes, int part, int nparts) {
-  constexpr int SP = 32 * W + 1;
   uint32_t* rows = ureg;                         // [128][4]
   uint64_t* q = (uint64_t*)(ureg + 512);         // [128][2]
   uint64_t* cm = (uint64_t*)(ureg + 1024);       // [KC_CMAX+1][2]
@@ -886,13 +904,12 @@ __device__ __forceinline__ uint64_t cdfs_dispatch(int l, const CNode& nd, uint64
 // Node of level l (2 <= l <= KC_CMAX) whose set C (lane-split `cw`) has at
 // most 64 members.  Candidates are dealt to the lanes of `nparts` waves
 // (this wave is `part`).  Returns this lane's share of the node's leaves.
-template <int W, bool PV>
+template <int W, bool PV, int SP>
 __device__ __forceinline__ uint64_t compressed_eval(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
                                                     const uint32_t* __restrict__ col, int s, int l, uint32_t cw,
                                                     int lane, uint16_t* __restrict__ mlist, uint64_t* __restrict__ rows,
                                                     uint64_t* __restrict__ rins, uint64_t& joins, uint64_t& nodes,
                                                     unsigned long long* cnt, int part, int nparts) {
-  constexpr int SP = 32 * W + 1;
   const int hiw = kc_wave_max_i32((lane < W && cw) ? lane : -1);
   if (hiw < 0) return 0;
   const int end = (hiw + 1) * 32 < s ? (hiw + 1) * 32 : s;
@@ -995,7 +1012,7 @@ __device__ __forceinline__ uint64_t compressed_eval(const uint32_t* __restrict__
 // 64 members, lane-parallel at levels 2 and 3, otherwise depth-first with an
 // explicit LDS stack whose children are evaluated the same way.  Returns this
 // lane's share of the node's leaves.
-template <int W, bool PV, bool COMP>
+template <int W, bool PV, bool COMP, int SP>
 __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* __restrict__ Bil,
                               const uint32_t* __restrict__ col, const int32_t* __restrict__ firstpos, int s, int L,
                               uint32_t cw, int lane, uint32_t* __restrict__ stk, int32_t* __restrict__ cur,
@@ -1004,24 +1021,23 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
                               uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes, uint64_t& wjoins,
                               uint64_t& cjoins, unsigned long long* cnt, int part, int nparts, int cmax, int clev,
                               int32_t* __restrict__ shared_next, uint32_t* __restrict__ ureg) {
-  constexpr int SP = 32 * W + 1;
   constexpr bool C2 = COMP && !PV && W >= 4 && W <= 16;
   const uint32_t m = split_popc(cw);
   if (COMP && (int)m <= cmax && (int)m <= 64 && L <= KC_CMAX && L >= clev) {
     const uint64_t j0 = joins;
-    const uint64_t t = compressed_eval<W, PV>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt,
+    const uint64_t t = compressed_eval<W, PV, SP>(Bl, Bil, col, s, L, cw, lane, mlist, rows, rins, joins, nodes, cnt,
                                               part, nparts);
     cjoins += joins - j0;
     return t;
   }
   if (L == 2) {
     uint64_t j = 0;
-    uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], cw, lane, j, cnt, part, nparts);
+    uint64_t t2 = leaf_eval<W, PV, SP>(Bl, Bil, s, firstpos[2], cw, lane, j, cnt, part, nparts);
     joins += (lane == 0) ? j : 0;
     return (lane == 0) ? t2 : 0;
   }
   if (L == 3)
-    return level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], cw, lane, vlist, joins, nodes, cnt, part, nparts);
+    return level3_eval<W, PV, SP>(Bl, Bil, s, firstpos[2], firstpos[3], cw, lane, vlist, joins, nodes, cnt, part, nparts);
   // depth-first.  With several waves on the node (nparts > 1) the top-level
   // candidates are taken from a shared counter, one at a time and from the
   // highest position down (those carry the most work), so that the waves
@@ -1084,17 +1100,17 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
       uint64_t tc;
       if (COMP && comp) {
         const uint64_t j0 = joins;
-        tc = compressed_eval<W, PV>(Bl, Bil, col, s, lc, nw, lane, mlist, rows, rins, joins, nodes, cnt, 0, 1);
+        tc = compressed_eval<W, PV, SP>(Bl, Bil, col, s, lc, nw, lane, mlist, rows, rins, joins, nodes, cnt, 0, 1);
         cjoins += joins - j0;
       } else if (C2 && comp2) {
         const uint64_t j0 = joins;
-        tc = compressed_eval2<W>(Bl, col, s, lc, nw, lane, ureg, joins, nodes, 0, 1);
+        tc = compressed_eval2<W, SP>(Bl, col, s, lc, nw, lane, ureg, joins, nodes, 0, 1);
         cjoins += joins - j0;
       } else if (lc == 3)
-        tc = level3_eval<W, PV>(Bl, Bil, s, firstpos[2], firstpos[3], nw, lane, vlist, joins, nodes, cnt, 0, 1);
+        tc = level3_eval<W, PV, SP>(Bl, Bil, s, firstpos[2], firstpos[3], nw, lane, vlist, joins, nodes, cnt, 0, 1);
       else {
         uint64_t j = 0;
-        uint64_t t2 = leaf_eval<W, PV>(Bl, Bil, s, firstpos[2], nw, lane, j, cnt, 0, 1);
+        uint64_t t2 = leaf_eval<W, PV, SP>(Bl, Bil, s, firstpos[2], nw, lane, j, cnt, 0, 1);
         joins += (lane == 0) ? j : 0;
         tc = (lane == 0) ? t2 : 0;
       }
@@ -1121,16 +1137,18 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
   return lane_acc;
 }
 
-template <int W, int NW, bool PV, bool COMP>
-// At least 4 waves per SIMD: the register budget stays at 128 VGPRs.
-__global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
-  using LY = ListLayout<W, NW, PV, COMP>;
+template <int W, int NW, bool PV, bool COMP, bool GB>
+// At least 4 waves per SIMD when the bitmaps sit in LDS: the register budget
+// stays at 128 VGPRs.  The device-memory layout (GB) serves the widest
+// classes, whose lane arrays of W words need more registers.
+__global__ __launch_bounds__(64 * NW, GB ? 1 : 4) void k_bitcol_list(ListArgs a) {
+  using LY = ListLayout<W, NW, PV, COMP, GB>;
   const int K = a.k + 1;
   constexpr int S = LY::S;
   constexpr int SP = LY::SP;
   extern __shared__ uint32_t lds[];
-  uint32_t* Bl = lds + LY::oB;
-  uint32_t* Bil = lds + LY::oBin;
+  const uint32_t* Bl = lds + LY::oB;
+  const uint32_t* Bil = lds + LY::oBin;
   uint32_t* col = lds + LY::oCol;
   int32_t* firstpos = (int32_t*)(lds + LY::oFirst);
   uint32_t* C0 = lds + LY::oC0;
@@ -1176,13 +1194,21 @@ __global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
       const int Sr = 32 * Wc;
       const int64_t bo = a.ri.boff[r], po = a.ri.poff[r];
       const int k = kc_vk(a.vk, a.roots[r], a.k);
-      // stage the root's bitmaps into LDS
-      for (int w = 0; w < W; ++w)
-        for (int p = tid; p < S; p += 64 * NW) {
-          bool in = w < Wc && p < Sr;
-          Bl[w * SP + p] = in ? a.B[bo + (int64_t)w * Sr + p] : 0u;
-          if (PV) Bil[w * SP + p] = in ? a.Bin[bo + (int64_t)w * Sr + p] : 0u;
-        }
+      // stage the root's bitmaps into LDS (or read them in place: the
+      // classes laid out in device memory have Wc = W, Sr = S)
+      if (GB) {
+        Bl = a.B + bo;
+        if (PV) Bil = a.Bin + bo;
+      } else {
+        uint32_t* Bw = lds + LY::oB;
+        uint32_t* Biw = lds + LY::oBin;
+        for (int w = 0; w < W; ++w)
+          for (int p = tid; p < S; p += 64 * NW) {
+            bool in = w < Wc && p < Sr;
+            Bw[w * SP + p] = in ? a.B[bo + (int64_t)w * Sr + p] : 0u;
+            if (PV) Biw[w * SP + p] = in ? a.Bin[bo + (int64_t)w * Sr + p] : 0u;
+          }
+      }
       for (int p = tid; p < S; p += 64 * NW) {
         col[p] = p < s ? (a.noprune ? 0xfffeu : (uint32_t)a.color[po + p]) : 0xffffu;
         if (PV) cnt[p] = 0;
@@ -1218,7 +1244,7 @@ __global__ __launch_bounds__(64 * NW, 4) void k_bitcol_list(ListArgs a) {
       __syncthreads();
       if (wid == 0) my_nodes += (lane == 0);
       const uint32_t c0w = lane < W ? C0[lane] : 0u;
-      const uint64_t wave_total = eval_node<W, PV, COMP>(Bl, Bil, col, firstpos, s, L0, c0w, lane, stk, cur, chosen, tot,
+      const uint64_t wave_total = eval_node<W, PV, COMP, SP>(Bl, Bil, col, firstpos, s, L0, c0w, lane, stk, cur, chosen, tot,
                                                    mlist, rows, rins, vlist, my_isect, my_nodes, my_wide, my_comp, cnt, wid, NW,
                                                    a.cmax, a.clev, &sh[2], ureg);
       {
@@ -1288,11 +1314,11 @@ struct EmitArgs {
   int* flags;
 };
 
-template <int W>
+template <int W, bool GB>
 struct EmitLayout {
   static constexpr int S = 32 * W;
-  static constexpr int SP = S + 1;
-  static constexpr int oStk = W * SP;                       // candidate sets, [KMAX][W]
+  static constexpr int SP = GB ? S : S + 1;
+  static constexpr int oStk = GB ? 0 : W * SP;              // candidate sets, [KMAX][W]
   static constexpr int oGid = oStk + KC_KMAX * W;            // position -> vertex id, [S]
   static constexpr int oFirst = oGid + S;                    // first position of each color, [KMAX+2]
   static constexpr int oChosen = oFirst + KC_KMAX + 2;       // vertex chosen at each level, [KMAX]
@@ -1300,12 +1326,12 @@ struct EmitLayout {
   static constexpr int words = oCur + KC_KMAX;
 };
 
-template <int W>
+template <int W, bool GB>
 __global__ __launch_bounds__(64) void k_bitcol_emit(EmitArgs a, const int32_t* __restrict__ list, int32_t nlist) {
-  using LY = EmitLayout<W>;
+  using LY = EmitLayout<W, GB>;
   constexpr int S = LY::S, SP = LY::SP;
   extern __shared__ uint32_t lds[];
-  uint32_t* Bl = lds;
+  const uint32_t* Bl = lds;
   uint32_t* stk = lds + LY::oStk;
   int32_t* gid = (int32_t*)(lds + LY::oGid);
   int32_t* firstpos = (int32_t*)(lds + LY::oFirst);
@@ -1321,8 +1347,12 @@ __global__ __launch_bounds__(64) void k_bitcol_emit(EmitArgs a, const int32_t* _
     const int Sr = 32 * Wc;
     const int64_t bo = a.ri.boff[r], po = a.ri.poff[r];
     const int k = kc_vk(a.vk, u, a.k);
-    for (int w = 0; w < W; ++w)
-      for (int p = lane; p < S; p += 64) Bl[w * SP + p] = (w < Wc && p < Sr) ? a.B[bo + (int64_t)w * Sr + p] : 0u;
+    if (GB) {
+      Bl = a.B + bo;  // the widest classes read the staged block in place (Wc = W)
+    } else {
+      for (int w = 0; w < W; ++w)
+        for (int p = lane; p < S; p += 64) lds[w * SP + p] = (w < Wc && p < Sr) ? a.B[bo + (int64_t)w * Sr + p] : 0u;
+    }
     for (int p = lane; p < S; p += 64) gid[p] = p < s ? a.perm[po + p] : -1;
     if (lane <= k + 1 && lane <= KC_KMAX + 1) {
       int lo = 0, hi = s;  // colors ascend with position
@@ -1399,10 +1429,10 @@ __global__ __launch_bounds__(64) void k_bitcol_emit(EmitArgs a, const int32_t* _
   if (lane == 0 && tot) kc_add_checked(a.count, tot, a.flags);
 }
 
-template <int W>
+template <int W, bool GB = false>
 static int launch_emit(const EmitArgs& a, const int32_t* list, int32_t nlist, hipStream_t st) {
-  const size_t bytes = 4 * (size_t)EmitLayout<W>::words;
-  auto fn = k_bitcol_emit<W>;
+  const size_t bytes = 4 * (size_t)EmitLayout<W, GB>::words;
+  auto fn = k_bitcol_emit<W, GB>;
   KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   int per_cu = 0;
   KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, bytes));
@@ -1652,9 +1682,9 @@ __global__ void k_add_counters(const unsigned long long* __restrict__ per_class,
 }
 
 // ============================================================== host side
-template <int W, int NW, bool PV>
+template <int W, int NW, bool PV, bool GB>
 static size_t list_lds_bytes(const ListArgs& a) {
-  return a.cmax > 0 ? ListLayout<W, NW, PV, true>::bytes(a.k + 1) : ListLayout<W, NW, PV, false>::bytes(a.k + 1);
+  return a.cmax > 0 ? ListLayout<W, NW, PV, true, GB>::bytes(a.k + 1) : ListLayout<W, NW, PV, false, GB>::bytes(a.k + 1);
 }
 
 static size_t device_max_lds() {
@@ -1675,11 +1705,11 @@ struct ListLaunch {
   size_t bytes = 0;
 };
 
-template <int W, int NW, bool PV>
+template <int W, int NW, bool PV, bool GB>
 static int resolve_list(const ListArgs& a, ListLaunch* L) {
   const bool comp = a.cmax > 0;
-  const size_t bytes = list_lds_bytes<W, NW, PV>(a);
-  auto fn = comp ? k_bitcol_list<W, NW, PV, true> : k_bitcol_list<W, NW, PV, false>;
+  const size_t bytes = list_lds_bytes<W, NW, PV, GB>(a);
+  auto fn = comp ? k_bitcol_list<W, NW, PV, true, GB> : k_bitcol_list<W, NW, PV, false, GB>;
   KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   int per_cu = 0;
   KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * NW, bytes));
@@ -1698,9 +1728,18 @@ template <int W, bool PV>
 static int resolve_list_nw(const ListArgs& a, int nw, ListLaunch* L) {
   // fewer waves per root when the requested shape's LDS does not fit
   const size_t lim = device_max_lds();
-  if (nw >= 8 && list_lds_bytes<W, 8, PV>(a) <= lim) return resolve_list<W, 8, PV>(a, L);
-  if (nw >= 2 && list_lds_bytes<W, 4, PV>(a) <= lim) return resolve_list<W, 4, PV>(a, L);
-  if (list_lds_bytes<W, 1, PV>(a) <= lim) return resolve_list<W, 1, PV>(a, L);
+  if (nw >= 8 && list_lds_bytes<W, 8, PV, false>(a) <= lim) return resolve_list<W, 8, PV, false>(a, L);
+  if (nw >= 2 && list_lds_bytes<W, 4, PV, false>(a) <= lim) return resolve_list<W, 4, PV, false>(a, L);
+  if (list_lds_bytes<W, 1, PV, false>(a) <= lim) return resolve_list<W, 1, PV, false>(a, L);
+  return KC_EUNSUPPORTED;
+}
+
+// Classes whose bitmaps stay in device memory: 8 or 1 waves per root.
+template <int W, bool PV>
+static int resolve_list_nw_dev(const ListArgs& a, int nw, ListLaunch* L) {
+  const size_t lim = device_max_lds();
+  if (nw >= 2 && list_lds_bytes<W, 8, PV, true>(a) <= lim) return resolve_list<W, 8, PV, true>(a, L);
+  if (list_lds_bytes<W, 1, PV, true>(a) <= lim) return resolve_list<W, 1, PV, true>(a, L);
   return KC_EUNSUPPORTED;
 }
 
@@ -1716,11 +1755,13 @@ static int resolve_list_class(const ListArgs& a, int cls, int nw, bool pv, ListL
     KC_CASE(4, 12)
     KC_CASE(5, 16)
     case 6:
-      if (pv) return KC_EUNSUPPORTED;
-      return resolve_list_nw<24, false>(a, nw, L);
+      return pv ? resolve_list_nw_dev<24, true>(a, nw, L) : resolve_list_nw<24, false>(a, nw, L);
     case 7:
-      if (pv) return KC_EUNSUPPORTED;
-      return resolve_list_nw<32, false>(a, nw, L);
+      return pv ? resolve_list_nw_dev<32, true>(a, nw, L) : resolve_list_nw<32, false>(a, nw, L);
+    case 8:
+      return pv ? resolve_list_nw_dev<48, true>(a, nw, L) : resolve_list_nw_dev<48, false>(a, nw, L);
+    case 9:
+      return pv ? resolve_list_nw_dev<64, true>(a, nw, L) : resolve_list_nw_dev<64, false>(a, nw, L);
   }
 #undef KC_CASE
   return KC_EUNSUPPORTED;
@@ -1806,7 +1847,7 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   if (R == 0) return KC_OK;
   const bool pv = c.pv != nullptr;
   const kc_options* opt = c.opt;
-  const int max_class = pv ? 5 : 7;
+  const int max_class = KC_NCLASS - 1;
   const bool timed = c.stats != nullptr && !c.size_only;
   EventPair ev_stage, ev_sched, ev_list;
   KC_TRY(ev_stage.init(timed));
@@ -1867,14 +1908,22 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     int32_t cnt = hoff[cl + 1] - hoff[cl];
     if (cnt <= 0) continue;
     int WM = kWClass[cl];
-    size_t bytes = stage_lds_bytes(WM, pv);
+    const bool in_dev = class_in_device_memory(cl, pv);
+    size_t bytes = stage_lds_bytes(WM, pv, !in_dev);
     auto fn = pv ? k_bitcol_stage<true> : k_bitcol_stage<false>;
     KC_HIP(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     int per_cu = 0;
     KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, bytes));
     int64_t grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * kc_device_cus() * 4;
+    uint32_t* mat = nullptr;
+    if (in_dev) {
+      // one adjacency matrix (two with per-vertex output) per workgroup
+      if (grid > 256) grid = 256;
+      if (grid > cnt) grid = cnt;
+      KC_TRY(scr.get(&mat, (size_t)grid * (pv ? 2 : 1) * (size_t)WM * 32 * WM));
+    }
     if (grid > cnt) grid = cnt;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), bytes, st, sa, byclass + hoff[cl], cnt, WM);
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64), bytes, st, sa, byclass + hoff[cl], cnt, WM, mat);
     KC_HIP(hipGetLastError());
   }
   KC_TRY(ev_stage.stop(st));
@@ -1904,6 +1953,8 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
         case 5: KC_TRY(launch_emit<16>(ea, lst, cnt, st)); break;
         case 6: KC_TRY(launch_emit<24>(ea, lst, cnt, st)); break;
         case 7: KC_TRY(launch_emit<32>(ea, lst, cnt, st)); break;
+        case 8: KC_TRY((launch_emit<48, true>(ea, lst, cnt, st))); break;
+        case 9: KC_TRY((launch_emit<64, true>(ea, lst, cnt, st))); break;
       }
     }
     return KC_OK;

@@ -1,23 +1,31 @@
 // kc_sdegree.hip -- SDegree (Alg. 5, Sec. 6.2) on gfx950.
 //
-// One wave per root u with d+_u >= k-1 (NodeParallel, Sec. 9).  The candidate
-// set C of every recursion level is a sorted list of vertex ids held in LDS
-// (or, for very large out-degrees, in a per-workgroup slice of device
-// memory).  The merge join of Alg. 5 -- C' = N+(x) intersected with C -- is
-// done with 64 lanes at a time: the lanes load 64 consecutive entries of the
-// sorted list N+(x) (one coalesced load), each lane looks its entry up in C by
-// binary search, and a ballot compacts the hits into the next level's list
-// in order (mbcnt gives each hit its slot).  The part of N+(x) below min(C)
-// is skipped with one binary search and the scan stops past max(C), so a
-// join touches only the range where matches can occur.  At l = 2 the hits
-// are only counted.  Pruning follows Alg. 5: x is skipped when d+_x <= l-2,
-// and a child list is entered only when it holds more than l-2 members.
-// Work is logged as |C| + d+_x per join, the cost term of Lemma 2.  When
-// counting, the joins of a level-2 node run lane-parallel instead (one
-// candidate per lane, each walking its own N+(x)), so that their memory
-// latencies overlap.
+// Work items are roots u with d+_u >= k-1 (NodeParallel, Sec. 9) or, for the
+// roots whose estimated work is heaviest, a root with its first candidate x
+// fixed (the edge (u, x): EdgeParallel, Sec. 10), so that no single heavy root
+// holds one wave for the whole run.  A persistent one-wave workgroup takes
+// items from a queue.  The candidate set C of every recursion level is a
+// sorted list of vertex ids held in LDS (or, for very large out-degrees, in a
+// per-workgroup slice of device memory).  The merge join of Alg. 5 -- C' =
+// N+(x) intersected with C -- is done with 64 lanes at a time: the lanes load
+// 64 consecutive entries of the sorted list N+(x) (one coalesced load), each
+// lane looks its entry up in C by binary search, and a ballot compacts the
+// hits into the next level's list in order (mbcnt gives each hit its slot).
+// The part of N+(x) below min(C) is skipped with one binary search and the
+// scan stops past max(C), so a join touches only the range where matches can
+// occur.  Pruning follows Alg. 5: x is skipped when d+_x <= l-2, and a child
+// list is entered only when it holds more than l-2 members.  Work is logged
+// as |C| + d+_x per join, the cost term of Lemma 2.
+//
+// When counting, a level-2 node's joins are flattened: every candidate x of
+// the node finds the range of N+(x) inside [min C, max C] (two binary
+// searches), the ranges are laid end to end, and each lane takes every 64th
+// entry of the concatenation, looks it up in C and counts the hits.  All
+// lanes stay busy whatever the lengths of the lists, and the loads of one
+// pass are independent of each other.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -42,7 +50,7 @@ struct SdArgs {
   const int32_t* drp;
   const int32_t* dcol;
   const int32_t* roots;
-  const int32_t* tasks;  // root indices in schedule order
+  const uint64_t* tasks;  // schedule order: (root index << 32) | (position of the fixed first candidate + 1, or 0)
   int32_t ntasks;
   unsigned long long* head;
   int chunk;
@@ -95,6 +103,7 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   unsigned long long* tot = (unsigned long long*)(((uintptr_t)(chosen + K) + 7) & ~(uintptr_t)7);
   const int lane = threadIdx.x;
   __shared__ int32_t sh_task[2];
+  __shared__ int32_t fl_lo[64], fl_off[65];  // flattened level-2 joins: range starts and offsets
 
   uint64_t my_nodes = 0, my_isect = 0, my_work = 0;  // per lane; summed over the wave per task
   for (;;) {
@@ -109,7 +118,9 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
     __syncthreads();
     if (t_lo >= t_hi) break;
     for (int32_t ti = t_lo; ti < t_hi; ++ti) {
-      const int32_t r = a.tasks[ti];
+      const uint64_t task = a.tasks[ti];
+      const int32_t r = (int32_t)(task >> 32);
+      const int32_t xp1 = (int32_t)(uint32_t)task;  // 0: the whole root
       const int32_t u = a.roots[r];
       const int32_t b0 = a.drp[u];
       const int32_t s0 = a.drp[u + 1] - b0;
@@ -121,20 +132,24 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           cnt[i] = 0;
         }
       }
+      // level 0 walks candidates [cur, end0): all of N+(u), or only the
+      // fixed one (the root's own call is then counted by the split pass)
+      const int end0 = xp1 ? xp1 : s0;
       if (lane == 0) {
-        cur[0] = 0;
+        cur[0] = xp1 ? xp1 - 1 : 0;
         size[0] = s0;
         tot[0] = 0;
       }
       __syncthreads();
-      my_nodes += (lane == 0);
+      my_nodes += (lane == 0 && !xp1);
       const int L0 = kt - 1;
       int d = 0;
       for (;;) {
         const int l = L0 - d;
         const int sz = size[d];
         const int c = cur[d];
-        if (c >= sz) {
+        const int end = d == 0 ? end0 : sz;
+        if (c >= end) {
           if (d == 0) break;
           unsigned long long T = tot[d];
           if (lane == 0) {
@@ -147,39 +162,80 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
         }
         int32_t* C = list + (size_t)d * SM;
         if (!PV && !EMIT && l == 2) {
-          // A level-2 node, lane-parallel: lane i takes candidate C[c + i]
-          // (and every 64th after it) and counts |N+(x) ∩ C| on its own,
-          // walking N+(x) within [min C, max C] with a moving binary search
-          // in C.  Same pruning, joins and work as the wave-wide join.
+          // A level-2 node, counted with flattened joins (same pruning,
+          // joins and work as one join per candidate).
           const int32_t cmin = C[0], cmax = C[sz - 1];
-          uint64_t node_total = 0;
-          for (int idx = c + lane; idx < sz; idx += 64) {
-            const int32_t x = C[idx];
-            const int32_t xb = a.drp[x], xe = a.drp[x + 1];
-            const int dx = xe - xb;
-            if (dx <= 0 && !a.noprune) continue;
-            my_isect++;
-            my_work += (uint64_t)sz + (uint64_t)dx;
-            int lo = xb, hi = xe;
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (a.dcol[mid] < cmin) lo = mid + 1; else hi = mid;
+          uint32_t hits = 0;
+          for (int b = c; b < end; b += 64) {
+            const int idx = b + lane;
+            int lo = 0, len = 0;
+            if (idx < end) {
+              const int32_t x = C[idx];
+              const int32_t xb = a.drp[x], xe = a.drp[x + 1];
+              const int dx = xe - xb;
+              if (dx > 0 || a.noprune) {
+                my_isect++;
+                my_work += (uint64_t)sz + (uint64_t)dx;
+                int l0 = xb, h0 = xe;
+                while (l0 < h0) {
+                  const int mid = (l0 + h0) >> 1;
+                  if (a.dcol[mid] < cmin) l0 = mid + 1; else h0 = mid;
+                }
+                int l1 = l0, h1 = xe;
+                while (l1 < h1) {
+                  const int mid = (l1 + h1) >> 1;
+                  if (a.dcol[mid] <= cmax) l1 = mid + 1; else h1 = mid;
+                }
+                lo = l0;
+                len = l1 - l0;
+              }
             }
-            int q = 0;
-            uint32_t hits = 0;
-            for (int i = lo; i < xe; ++i) {
-              const int32_t y = a.dcol[i];
-              if (y > cmax) break;
-              q = sd_lower_bound(C, q, sz, y);
-              if (q >= sz) break;
-              hits += C[q] == y;
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+              const int y = __shfl_up(incl, o, 64);
+              if (lane >= o) incl += y;
             }
-            node_total += hits;
+            const int total_len = __shfl(incl, 63, 64);
+            fl_lo[lane] = lo;
+            fl_off[lane] = incl - len;
+            if (lane == 63) fl_off[64] = incl;
+            kc_wave_lds_sync();
+            for (int t0 = 0; t0 < total_len; t0 += 128) {
+              // two entries per lane per pass, both loads issued first
+              const int ta = t0 + lane, tb = t0 + 64 + lane;
+              int32_t ya = 0x7fffffff, yb = 0x7fffffff;
+              if (ta < total_len) {
+                int p0 = 0, p1 = 65;
+                while (p0 < p1) {
+                  const int mid = (p0 + p1) >> 1;
+                  if (fl_off[mid] <= ta) p0 = mid + 1; else p1 = mid;
+                }
+                ya = a.dcol[fl_lo[p0 - 1] + (ta - fl_off[p0 - 1])];
+              }
+              if (tb < total_len) {
+                int p0 = 0, p1 = 65;
+                while (p0 < p1) {
+                  const int mid = (p0 + p1) >> 1;
+                  if (fl_off[mid] <= tb) p0 = mid + 1; else p1 = mid;
+                }
+                yb = a.dcol[fl_lo[p0 - 1] + (tb - fl_off[p0 - 1])];
+              }
+              if (ta < total_len) {
+                const int q = sd_lower_bound(C, 0, sz, ya);
+                hits += (q < sz && C[q] == ya);
+              }
+              if (tb < total_len) {
+                const int q = sd_lower_bound(C, 0, sz, yb);
+                hits += (q < sz && C[q] == yb);
+              }
+            }
+            kc_wave_lds_sync();  // the ranges are rewritten by the next batch
           }
-          const uint64_t T2 = kc_wave_sum_u64(node_total);
+          const uint64_t T2 = kc_wave_sum_u64(hits);
           if (lane == 0) {
             tot[d] += (unsigned long long)T2;
-            cur[d] = sz;
+            cur[d] = end;
           }
           kc_wave_lds_sync();
           continue;
@@ -294,8 +350,18 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   }
 }
 
-__global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp, int k0,
-                          const int32_t* vk, int32_t* bin, int* flags) {
+#define SD_LOGW_BINS 512
+#define SD_LOGW_SCALE 8.0f
+
+__device__ __forceinline__ float sd_log_binom(float n, float k) {
+  if (k > n) return -1.0f;
+  return lgammaf(n + 1.0f) - lgammaf(k + 1.0f) - lgammaf(n - k + 1.0f);
+}
+
+// Per root: candidate-list class and the degree schedule's work estimate
+// log C(d+, k-1) (a histogram per class sets the split threshold).
+__global__ void k_sd_est(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp, int k0,
+                         const int32_t* vk, int32_t* cls, float* logw, int32_t* hist, int32_t* cls_max, int* flags) {
   int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   int32_t u = roots[r];
@@ -306,9 +372,74 @@ __global__ void k_sd_bins(int32_t R, const int32_t* __restrict__ roots, const in
     atomicOr(flags, KC_FLAG_TOOBIG);
     c = 0;
   }
-  // degree schedule: larger d+ first inside a class
-  float lw = lgammaf((float)s + 1.f) - lgammaf((float)k) - lgammaf((float)(s - k + 2));
-  bin[r] = c * 64 + 63 - kc_key_q(lw);
+  float lw = sd_log_binom((float)s, (float)(k - 1));
+  if (!(lw > -1e30f)) lw = 0.f;
+  cls[r] = c;
+  logw[r] = lw;
+  int b = (int)(lw * SD_LOGW_SCALE);
+  b = b < 0 ? 0 : (b >= SD_LOGW_BINS ? SD_LOGW_BINS - 1 : b);
+  atomicAdd(&hist[c * SD_LOGW_BINS + b], 1);
+  atomicMax(&cls_max[c], s);
+}
+
+struct SdSplit {
+  int thr[SD_NCLASS];  // split a root of this class when its estimate bin is >= thr
+};
+
+// Work items: a whole root, or, for a root to split, one item per candidate
+// x of its top call that Alg. 5 does not skip (d+_x > k-3), in schedule
+// order (heaviest first inside each class).  Mode 0 counts, mode 1 writes;
+// the split roots' own calls are counted here.
+__global__ void k_sd_tasks(int32_t R, const int32_t* __restrict__ roots, const int32_t* __restrict__ drp,
+                           const int32_t* __restrict__ dcol, int k0, const int32_t* vk,
+                           const int32_t* __restrict__ cls, const float* __restrict__ logw, SdSplit sp, int noprune,
+                           int mode, unsigned long long* ntasks, uint64_t* tasks, int32_t* task_bin,
+                           unsigned long long* counters) {
+  const int lane = kc_lane();
+  const int32_t wave = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / KC_WAVE);
+  if (wave >= R) return;
+  const int32_t r = wave;
+  const int32_t u = roots[r];
+  const int k = kc_vk(vk, u, k0);
+  const int c = cls[r];
+  const bool split = k >= 4 && (int)(logw[r] * SD_LOGW_SCALE) >= sp.thr[c];
+  if (!split) {
+    if (lane == 0) {
+      unsigned long long o = atomicAdd(ntasks, 1ull);
+      if (mode == 1) {
+        tasks[o] = (uint64_t)(uint32_t)r << 32;
+        task_bin[o] = c * 64 + 63 - kc_key_q(logw[r]);
+      }
+    }
+    return;
+  }
+  const int32_t b0 = drp[u], s = drp[u + 1] - b0;
+  for (int32_t i0 = 0; i0 < s; i0 += KC_WAVE) {
+    const int32_t i = i0 + lane;
+    int dx = 0;
+    bool take = false;
+    if (i < s) {
+      const int32_t x = dcol[b0 + i];
+      dx = drp[x + 1] - drp[x];
+      take = noprune || dx > k - 3;
+    }
+    const uint64_t m = kc_ballot(take);
+    unsigned long long base = 0;
+    if (lane == 0 && m) base = atomicAdd(ntasks, (unsigned long long)__popcll(m));
+    base = (unsigned long long)__shfl((long long)base, 0, 64);
+    if (mode == 1 && take) {
+      const unsigned long long o = base + (unsigned long long)kc_mbcnt(m);
+      tasks[o] = ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(i + 1);
+      task_bin[o] = c * 64 + 63 - kc_key_q(sd_log_binom((float)(dx < s ? dx : s), (float)(k - 2)));
+    }
+  }
+  if (mode == 1 && lane == 0) atomicAdd(&counters[0], 1ull);  // the root's own call
+}
+
+__global__ void k_sd_gather(const uint64_t* __restrict__ in, const int32_t* __restrict__ order, int32_t n,
+                            uint64_t* out) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[order[i]];
 }
 
 __global__ void k_sd_add_counters(const unsigned long long* __restrict__ per_class, int ncls,
@@ -325,18 +456,83 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   const int32_t R = c.nroots;
   if (R == 0) return KC_OK;
   const bool pv = c.pv != nullptr;
-  int32_t *bin, *order;
-  KC_TRY(scr.get(&bin, R));
-  KC_TRY(scr.get(&order, R));
-  k_sd_bins<<<(R + 255) / 256, 256, 0, st>>>(R, c.roots, c.drp, c.k, c.vk, bin, c.flags);
+  const kc_options* opt = c.opt;
+  int32_t *cls, *hist;
+  float* logw;
+  KC_TRY(scr.get(&cls, R));
+  KC_TRY(scr.get(&logw, R));
+  // per class: the estimate histogram, then the class's largest out-degree
+  KC_TRY(scr.get(&hist, SD_NCLASS * SD_LOGW_BINS + SD_NCLASS));
+  KC_HIP(hipMemsetAsync(hist, 0, sizeof(int32_t) * (SD_NCLASS * SD_LOGW_BINS + SD_NCLASS), st));
+  k_sd_est<<<(R + 255) / 256, 256, 0, st>>>(R, c.roots, c.drp, c.k, c.vk, cls, logw, hist,
+                                            hist + SD_NCLASS * SD_LOGW_BINS, c.flags);
   KC_HIP(hipGetLastError());
-  const int NB = SD_NCLASS * 64;
-  std::vector<int32_t> boff(NB + 1);
-  KC_TRY(kc_bin_sort(bin, R, NB, order, boff.data(), scr, st));
+  std::vector<int32_t> hh(SD_NCLASS * SD_LOGW_BINS + SD_NCLASS);
   int hflags = 0;
+  KC_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * hh.size(), hipMemcpyDeviceToHost, st));
   KC_HIP(hipMemcpyAsync(&hflags, c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
   KC_HIP(hipStreamSynchronize(st));
   if (hflags & KC_FLAG_TOOBIG) return KC_EUNSUPPORTED;
+  // Which roots are split into one item per top-level candidate: per class,
+  // those whose estimate exceeds 1/(8 slots) of the class's estimated total
+  // (shares, the default), the slots/4 + 4 slots heaviest (fixed counts), or
+  // those above an explicit threshold; never with split = -1.
+  const int slots = kc_device_cus() * 4;
+  const int policy = opt && opt->split_policy > 0 ? opt->split_policy : 2;
+  if (policy > 2) return KC_EINVAL;
+  SdSplit sp;
+  for (int cl = 0; cl < SD_NCLASS; ++cl) {
+    const int32_t* h = hh.data() + cl * SD_LOGW_BINS;
+    int thr = SD_LOGW_BINS;
+    if (opt && opt->split < 0) {
+      thr = SD_LOGW_BINS + 1;
+    } else if (opt && opt->split_threshold > 0.f) {
+      thr = (int)(opt->split_threshold * SD_LOGW_SCALE);
+    } else if (policy == 2) {
+      double tot = 0.0;
+      for (int b = 0; b < SD_LOGW_BINS; ++b) tot += (double)h[b] * exp((b + 0.5) / SD_LOGW_SCALE);
+      const double target = tot / (8.0 * slots);
+      if (target > 1.0) thr = (int)(log(target) * SD_LOGW_SCALE) + 1;
+    } else {
+      const int64_t want = (int64_t)slots / 4 + (int64_t)slots * 4;
+      int64_t cum = 0;
+      for (int b = SD_LOGW_BINS - 1; b >= 0; --b) {
+        cum += h[b];
+        if (cum >= want) { thr = b + 1; break; }
+      }
+    }
+    sp.thr[cl] = thr;
+  }
+  const int noprune = opt && (opt->disable & KC_NO_PRUNE) ? 1 : 0;
+  unsigned long long* ntask_dev;
+  KC_TRY(scr.get(&ntask_dev, 2));
+  KC_HIP(hipMemsetAsync(ntask_dev, 0, sizeof(unsigned long long), st));
+  const unsigned tgrid = (unsigned)(((int64_t)R * KC_WAVE + 255) / 256);
+  k_sd_tasks<<<tgrid, 256, 0, st>>>(R, c.roots, c.drp, c.dcol, c.k, c.vk, cls, logw, sp, noprune, 0, ntask_dev,
+                                    nullptr, nullptr, c.counters);
+  KC_HIP(hipGetLastError());
+  unsigned long long nt_h = 0;
+  KC_HIP(hipMemcpyAsync(&nt_h, ntask_dev, sizeof(nt_h), hipMemcpyDeviceToHost, st));
+  KC_HIP(hipStreamSynchronize(st));
+  if (nt_h >= (unsigned long long)INT32_MAX) return KC_EUNSUPPORTED;
+  const int32_t NT = (int32_t)nt_h;
+  uint64_t *tasks, *tasks_sorted;
+  int32_t *task_bin, *order;
+  KC_TRY(scr.get(&tasks, (size_t)NT + 1));
+  KC_TRY(scr.get(&tasks_sorted, (size_t)NT + 1));
+  KC_TRY(scr.get(&task_bin, (size_t)NT + 1));
+  KC_TRY(scr.get(&order, (size_t)NT + 1));
+  KC_HIP(hipMemsetAsync(ntask_dev, 0, sizeof(unsigned long long), st));
+  k_sd_tasks<<<tgrid, 256, 0, st>>>(R, c.roots, c.drp, c.dcol, c.k, c.vk, cls, logw, sp, noprune, 1, ntask_dev,
+                                    tasks, task_bin, c.counters);
+  KC_HIP(hipGetLastError());
+  const int NB = SD_NCLASS * 64;
+  std::vector<int32_t> boff(NB + 1);
+  KC_TRY(kc_bin_sort(task_bin, NT, NB, order, boff.data(), scr, st));
+  if (NT > 0) {
+    k_sd_gather<<<(NT + 255) / 256, 256, 0, st>>>(tasks, order, NT, tasks_sorted);
+    KC_HIP(hipGetLastError());
+  }
   unsigned long long* heads;
   KC_TRY(scr.get(&heads, SD_NCLASS));
   KC_HIP(hipMemsetAsync(heads, 0, sizeof(unsigned long long) * SD_NCLASS, st));
@@ -373,14 +569,20 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     a.drp = c.drp;
     a.dcol = c.dcol;
     a.roots = c.roots;
-    a.tasks = order + lo;
+    a.tasks = tasks_sorted + lo;
     a.ntasks = hi - lo;
     a.head = heads + cl;
     a.chunk = c.opt && c.opt->chunk > 0 ? c.opt->chunk : (cl <= 1 ? 8 : 1);
     a.k = c.k;
     a.vk = c.vk;
     a.root_count = c.root_count;
-    a.SMAX = kSClass[cl];
+    // lists sized for the class's largest out-degree (rounded up to 64), not
+    // the class bound: the LDS per wave sets how many waves share a CU
+    {
+      const int cm = hh[SD_NCLASS * SD_LOGW_BINS + cl];
+      const int fit = (cm + 63) & ~63;
+      a.SMAX = fit > 0 && fit < kSClass[cl] ? fit : kSClass[cl];
+    }
     a.count = c.count;
     a.pv = c.pv;
     a.counters = cls_ctr + 3 * cl;
@@ -427,7 +629,7 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     KC_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     c.stats->list_ms += ms;
     c.stats->list_launches += launches;
-    c.stats->n_tasks += R;
+    c.stats->n_tasks += NT;
     unsigned long long hc[3 * SD_NCLASS];
     KC_HIP(hipMemcpyAsync(hc, cls_ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
     KC_HIP(hipStreamSynchronize(st));

@@ -32,7 +32,7 @@ def test_status_strings_without_device():
 
 def test_struct_layouts_match_header():
     # sizes fixed by the header's field order on x86-64
-    assert ctypes.sizeof(kc.Stats) == 5 * 8 + 2 * 4 + 8 + 2 * 4 + 8 * 8 + 3 * 8 * 8
+    assert ctypes.sizeof(kc.Stats) == 5 * 8 + 2 * 4 + 8 + 2 * 4 + 8 * 8 + 3 * 10 * 8
     assert kc.Options.stats.offset == ctypes.sizeof(kc.Options) - 8
 
 

@@ -354,3 +354,25 @@ def test_root_attribution_sums_to_the_total():
             want = oracle.count(*g, k)
             assert out.value == want
             assert int(rc.sum().item()) == want
+
+
+@pytest.mark.parametrize("order", ["degree", "core"])
+def test_sdegree_split_does_not_change_results(order):
+    """SDegree's heavy roots split into (root, first candidate) items: counts,
+    per-vertex values, per-root joins and work and the number of calls equal
+    the oracle's instrumented recursion under every split setting."""
+    g = graphgen.chung_lu(5000, 12.0, 2.1, 600.0, planted=[40, 30, 25], seed=8)
+    for k in (4, 6):
+        want, wpv = oracle.count(*g, k, per_vertex=True)
+        total, pl, per = oracle.method_count(*g, k, order)
+        assert total == want
+        for kw in [dict(), dict(split=-1), dict(split_threshold=1.0), dict(split_policy=1),
+                   dict(split_threshold=0.5, chunk=4)]:
+            say("sdegree split", order, k, kw)
+            c, st, lg = _logs(g, k, order, **kw)
+            assert c == want, kw
+            assert np.array_equal(lg["isect"], per["isect"].astype(np.int64)), kw
+            assert np.array_equal(lg["work"], per["work"].astype(np.int64)), kw
+            assert st["nodes"] == int(per["nodes"].sum()), kw
+            cc, pv = gpv(g, k, order, **kw)
+            assert cc == want and np.array_equal(pv, wpv.astype(np.int64)), kw

@@ -1,7 +1,7 @@
 """Wide local subgraphs: every bitmap word class of the BitCol listing kernel
-(1 to 32 words of 32 bits, local subgraphs of up to 1024 vertices) and every
-candidate-list class of SDegree, including its device-memory lists, against
-closed forms.
+(1 to 64 words of 32 bits, local subgraphs of up to 2048 vertices; the widest
+classes keep their bitmaps in device memory) and every candidate-list class of
+SDegree, including its device-memory lists, against closed forms.
 
 K_n minus one edge survives Pre-Core and Pre-List (it is not a clique), and
 under the degeneracy order its roots have every out-degree from 0 to n-2, so
@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_2203_13512_amd as kc  # noqa: E402
 
-WORDS = [1, 2, 4, 8, 12, 16, 24, 32]
+WORDS = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
 
 
 def say(*a):
@@ -48,7 +48,7 @@ def minus_edge_pv(n, k, a=0, b=1):
 
 
 def classes_run(st):
-    return [WORDS[c] for c in range(8) if st["class_tasks"][c] > 0]
+    return [WORDS[c] for c in range(10) if st["class_tasks"][c] > 0]
 
 
 LAUNCH = [dict(), dict(waves_per_root=1), dict(waves_per_root=4, chunk=4), dict(compress=-1),
@@ -65,7 +65,7 @@ def test_every_word_class_complete_minus_edge(k):
         say("K_n - e", n, k, kw)
         c, st = kc.count(*g, k, "color", stats=True, **kw)
         assert c == want, kw
-        assert classes_run(st) == WORDS, classes_run(st)
+        assert classes_run(st) == WORDS[:8], classes_run(st)
         assert st["max_out_degree"] == n - 2
 
 
@@ -89,7 +89,7 @@ def test_every_word_class_cocktail_party(k):
         say("cocktail party", r, k, kw)
         c, st = kc.count(*g, k, "color", stats=True, **kw)
         assert c == 2 ** k * math.comb(r, k), kw
-        assert classes_run(st) == WORDS
+        assert classes_run(st) == WORDS[:8]
 
 
 @pytest.mark.parametrize("k", [4, 5])
@@ -121,14 +121,44 @@ def test_sdegree_device_memory_lists():
     assert np.array_equal(pv.cpu().numpy(), minus_edge_pv(n, 4))
 
 
+@pytest.mark.parametrize("n", [1030, 1600, 2050])
+def test_local_subgraphs_in_device_memory(n):
+    """Local subgraphs of 1025..2048 vertices (48- and 64-word bitmaps) are
+    staged and listed with their bitmaps in device memory; per-vertex output
+    above 512 local vertices (24 and 32 words and beyond) likewise."""
+    g = dev(G.complete_minus_edge(n, 2, n - 3))
+    for kw in [dict(), dict(waves_per_root=1), dict(compress=-1), dict(split=2, split_threshold=1.0)]:
+        say("device-memory bitmaps", n, kw)
+        c, st = kc.count(*g, 4, "color", stats=True, **kw)
+        assert c == minus_edge_count(n, 4), kw
+        assert st["max_out_degree"] == n - 2
+        assert st["class_tasks"][8 if n <= 1538 else 9] > 0
+    c, pv = kc.count(*g, 4, "color", per_vertex=True)
+    assert c == minus_edge_count(n, 4)
+    assert np.array_equal(pv.cpu().numpy(), minus_edge_pv(n, 4, 2, n - 3))
+    # listing from the device-memory classes: a bounded buffer of valid,
+    # distinct triangles (the missing edge (2, n-3) is in none of them)
+    rows, total = kc.list_cliques(*g, 3, "color", capacity=1000)
+    assert total == minus_edge_count(n, 3) and rows.shape == (1000, 3)
+    r = np.sort(rows.cpu().numpy(), axis=1)
+    assert len({tuple(x) for x in r}) == 1000
+    assert np.all((r[:, 0] < r[:, 1]) & (r[:, 1] < r[:, 2]) & (r[:, 0] >= 0) & (r[:, 2] < n))
+    assert not np.any(np.isin(r, [2]).any(axis=1) & np.isin(r, [n - 3]).any(axis=1))
+
+
+def test_per_vertex_classes_beyond_512_local_vertices():
+    n = 800  # out-degrees up to 798: per-vertex classes of 24 and 32 words
+    g = dev(G.complete_minus_edge(n, 0, 500))
+    for k in (4, 5):
+        c, pv, st = kc.count(*g, k, "color", per_vertex=True, stats=True)
+        assert c == minus_edge_count(n, k)
+        assert np.array_equal(pv.cpu().numpy(), minus_edge_pv(n, k, 0, 500))
+        assert st["class_tasks"][6] > 0 and st["class_tasks"][7] > 0
+
+
 def test_local_subgraphs_beyond_the_supported_size_are_reported():
-    """Counting takes local subgraphs of up to 1024 vertices, per-vertex
-    output up to 512; larger ones are refused, not truncated."""
-    g = dev(G.complete_minus_edge(1030))
+    """Local subgraphs of more than 2048 vertices are refused, not truncated."""
+    g = dev(G.complete_minus_edge(2060))
     with pytest.raises(kc.KCliqueError) as e:
-        kc.count(*g, 4, "color")
-    assert e.value.status == kc.EUNSUPPORTED
-    g = dev(G.complete_minus_edge(520))
-    with pytest.raises(kc.KCliqueError) as e:
-        kc.count(*g, 4, "color", per_vertex=True)
+        kc.count(*g, 3, "color")
     assert e.value.status == kc.EUNSUPPORTED
