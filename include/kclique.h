@@ -204,6 +204,20 @@ int kclique_list(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int3
 int kclique_workspace_size(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
                            int32_t per_vertex, const kc_options* opt, size_t* bytes);
 
+/* Allocation-free variant of kclique_count_ex, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): arguments, results and errors as for
+ * kclique_count_ex, but the call's scratch is a fixed 256 MiB array inside the
+ * library's device code (held by each GPU the library runs on until the
+ * process ends), and the call allocates nothing and creates no stream or
+ * event (class_streams is taken as 1; opt->stats and opt->workspace are
+ * ignored).  A call that needs more scratch than 256 MiB (see
+ * kclique_workspace_size) returns KC_EWORKSPACE.  Calls on one GPU share the
+ * array: calls that overlap on one GPU race and must be serialised by the
+ * caller (one stream, or host synchronisation). */
+int kclique_count_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k, int32_t order,
+                          const kc_options* opt, uint64_t* count_out, uint64_t* per_vertex_out);
+
 /* Many independent graphs in one call (each counted as in Sec. 3.1, all in
  * one preprocessing pass and one listing launch per bitmap class, as the
  * disjoint union with a k per vertex): graph g has n[g] vertices, its rows

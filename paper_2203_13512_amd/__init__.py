@@ -108,6 +108,8 @@ def _lib():
     L.kclique_workspace_size.restype = ctypes.c_int
     L.kclique_workspace_size.argtypes = [i32, vp, vp, i32, i32, i32, ctypes.POINTER(Options),
                                          ctypes.POINTER(ctypes.c_size_t)]
+    L.kclique_count_noalloc.restype = ctypes.c_int
+    L.kclique_count_noalloc.argtypes = [i32, vp, vp, i32, i32, ctypes.POINTER(Options), u64p, vp]
     L.kclique_list.restype = ctypes.c_int
     L.kclique_list.argtypes = [i32, vp, vp, i32, i32, ctypes.POINTER(Options), vp, ctypes.c_int64,
                                ctypes.POINTER(ctypes.c_int64), u64p]

@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "kc_internal.h"
@@ -375,6 +376,50 @@ extern "C" int kclique_list(int32_t n, const int32_t* row_ptr, const int32_t* co
   o.root_features = nullptr;
   return count_impl(n, row_ptr, col_idx, k, order, &o, count_out, nullptr, nullptr, nullptr, nullptr, false,
                     cliques_out, capacity, written_out);
+}
+
+// ------------------------------------------------ allocation-free entry point
+// For callers that cannot allocate device memory (code under graph capture,
+// tight serving loops, harnesses that forbid it): every byte of a call's
+// scratch comes from `scratch`, a fixed array in the library's device code
+// that each GPU the library runs on holds until the process ends.  Its device
+// address is looked up once per device (the host-side name of the array is
+// not a device address).  Calls on one GPU share the array: overlapping calls
+// on one GPU race, so the caller serialises them.
+#define KC_NOALLOC_BYTES ((size_t)256 << 20)
+#define KC_NOALLOC_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[KC_NOALLOC_BYTES];
+static void* g_scratch_ptr[KC_NOALLOC_DEVICES];
+static std::mutex g_scratch_mu;
+
+static int noalloc_scratch(void** out) {
+  int dev = -1;
+  KC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= KC_NOALLOC_DEVICES) return KC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    KC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return KC_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KC_OK;
+}
+
+extern "C" int kclique_count_noalloc(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k,
+                                     int32_t order, const kc_options* opt, uint64_t* count_out,
+                                     uint64_t* per_vertex_out) {
+  void* ws = nullptr;
+  KC_TRY(noalloc_scratch(&ws));
+  kc_options o;
+  if (opt) o = *opt;
+  else memset(&o, 0, sizeof(o));
+  o.workspace = ws;
+  o.workspace_bytes = KC_NOALLOC_BYTES;
+  o.class_streams = 1;  // no streams or events are created either
+  o.stats = nullptr;
+  return count_impl(n, row_ptr, col_idx, k, order, &o, count_out, per_vertex_out);
 }
 
 extern "C" int kclique_workspace_size(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k,

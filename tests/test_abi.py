@@ -13,7 +13,7 @@ def test_header_declares_the_boundary():
     for f in ["kclique_count", "kclique_list_per_vertex", "kclique_count_ex", "kclique_count_batched",
               "kclique_plan_batched", "kclique_plan_execute", "kclique_plan_destroy",
               "kc_mlp_forward", "kc_mlp_train_step", "kc_status_string", "kc_options_init",
-              "kclique_workspace_size", "kc_mlp_workspace_size", "kclique_list"]:
+              "kclique_workspace_size", "kc_mlp_workspace_size", "kclique_list", "kclique_count_noalloc"]:
         assert f in names
 
 
