@@ -73,7 +73,7 @@ VARIANTS = {
 def listing_sources_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kc_bitcol.hip", "kc_internal.h"):
+    for f in ("kc_bitcol.h", "kc_bitcol.hip", "kc_internal.h"):
         with open(os.path.join(ROOT, "paper_2203_13512_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkclique.so")
-SOURCES = ["kc_api.hip", "kc_prep.hip", "kc_sched.hip", "kc_bitcol.hip", "kc_sdegree.hip", "kc_mlp.hip"]
+SOURCES = ["kc_api.hip", "kc_prep.hip", "kc_sched.hip", "kc_bitcol.hip", "kc_bitcol_wide.hip", "kc_sdegree.hip",
+           "kc_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
