@@ -57,8 +57,8 @@ WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
 # 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE
 # and WRITE_SIZE, each scaled by what the same counter reads for a plain copy
 # of known size), valid only for the kernel sources they were taken on.
-PROFILED_TRAFFIC = {"sources_sha256_16": "18e5b7998d7ebe7e", "word_class": 16,
-                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.70e9,
+PROFILED_TRAFFIC = {"sources_sha256_16": "14a5005064571ea6", "word_class": 16,
+                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.47e9,
                     "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md"}
 
 VARIANTS = {
