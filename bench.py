@@ -135,6 +135,32 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
+SD_CLASSES = [64, 256, 1024, 4096, 16384, 65536]
+
+
+def roofline_sdegree(st_list):
+    """Roofline of SDegree's dominant listing launch: Lemma 2's cost |C| + d+_x
+    elements per merge join, 4 bytes each (the elements a join must read),
+    against the HBM peak."""
+    ncls = len(SD_CLASSES)
+    cms = [statistics.fmean(st["class_ms"][c] for st in st_list) for c in range(ncls)]
+    dom = max(range(ncls), key=lambda c: cms[c])
+    st = st_list[-1]
+    byts = 4.0 * st["class_work"][dom]
+    achieved = byts / (cms[dom] / 1e3) / 1e9 if cms[dom] > 0 else 0.0
+    list_ms = statistics.fmean(s["list_ms"] for s in st_list)
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 5), "traffic": None,
+            "kernel": f"k_sdegree_list, candidate lists of up to {SD_CLASSES[dom]} entries",
+            "launch_ms": round(cms[dom], 3), "launches_averaged": len(st_list),
+            "lemma2_elements": int(st["class_work"][dom]), "tasks": int(st["class_tasks"][dom]),
+            "all_classes": {str(SD_CLASSES[c]): {"ms": round(cms[c], 3), "elements": int(st["class_work"][c]),
+                                                 "tasks": int(st["class_tasks"][c])}
+                            for c in range(ncls) if st["class_tasks"][c] > 0},
+            "list_ms": round(list_ms, 3), "joins": int(st["isect"]),
+            "chip_achieved": round(4.0 * st["work"] / (list_ms / 1e3) / 1e9, 2)}
+
+
 def roofline_of(st_list, w_name, k, variant):
     """Roofline of the dominant listing launch: the word class whose
     persistent kernel ran longest (one launch per class per step; durations
@@ -282,7 +308,8 @@ def main():
                               "steps": len(r["times"]), "n_tasks": r["stats"][-1]["n_tasks"],
                               "launch": {key: val for key, val in kwargs[v].items() if key != "mlp"}}
                           for v, r in done.items()},
-            "roofline": roofline_of(R["stats"], w.name, k, head),
+            "roofline": (roofline_of(R["stats"], w.name, k, head) if args.order == "color"
+                         else roofline_sdegree(R["stats"])),
             "cpu_baseline": cpu,
             # context only: the paper reports speedups of its methods over its
             # own CPU baselines (total serial time over its ten datasets), no rates

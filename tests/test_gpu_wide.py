@@ -61,7 +61,9 @@ def test_every_word_class_complete_minus_edge(k):
     n = 1000
     g = dev(G.complete_minus_edge(n))
     want = minus_edge_count(n, k)
-    for kw in LAUNCH:
+    # every launch shape at k = 4; at k = 5 (40x the joins) three of them
+    for kw in (LAUNCH if k == 4 else [dict(), dict(split=2, split_threshold=1.0, waves_per_root=8),
+                                      dict(class_streams=2)]):
         say("K_n - e", n, k, kw)
         c, st = kc.count(*g, k, "color", stats=True, **kw)
         assert c == want, kw
@@ -85,7 +87,8 @@ def test_every_word_class_k6_and_learned_schedule():
 def test_every_word_class_cocktail_party(k):
     r = 500
     g = dev(G.cocktail_party(r))
-    for kw in [dict(), dict(compress=-1), dict(waves_per_root=4, split=2, split_threshold=1.0)]:
+    for kw in ([dict(), dict(compress=-1), dict(waves_per_root=4, split=2, split_threshold=1.0)] if k == 4
+               else [dict(waves_per_root=4, split=2, split_threshold=1.0)]):
         say("cocktail party", r, k, kw)
         c, st = kc.count(*g, k, "color", stats=True, **kw)
         assert c == 2 ** k * math.comb(r, k), kw
