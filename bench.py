@@ -59,7 +59,12 @@ WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
 # of known size), valid only for the kernel sources they were taken on.
 PROFILED_TRAFFIC = {"sources_sha256_16": "14a5005064571ea6", "word_class": 16,
                     "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 18.47e9,
-                    "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md"}
+                    "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md",
+                    # SQ_INSTS_VALU of the same launch and its duration in that run
+                    "valu_wave_insts": 8.330e12, "valu_launch_ms": 14179.8,
+                    "valu_summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_sq_counters.md"}
+# one wave64 VALU instruction per CU per clock: 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK_PER_S = 256 * 2.4e9
 
 VARIANTS = {
     "learned": dict(schedule="learned", class_streams=1),
@@ -89,32 +94,56 @@ _CPU_JOB = None
 def _cpu_worker(i_p):
     import oracle
     i, p, secs = i_p
-    rp, ci, k, perm = _CPU_JOB
-    return oracle.count_roots(rp, ci, k, perm[i::p], seconds=secs)[:2]
+    drp, dci, k, roots = _CPU_JOB
+    return oracle.bitcol_count_roots(drp, dci, k, roots[i::p], seconds=secs)[:2]
 
 
-def cpu_baseline(rp_h, ci_h, k, secs):
-    """The oracle's ordered recursion on the host's cores: each worker process
-    takes every p-th root of one fixed random order and runs for `secs`."""
+def _cpu_worker_sdegree(i_p):
+    import oracle
+    i, p, secs = i_p
+    drp, dci, k, roots = _CPU_JOB
+    return oracle.sdegree_count_roots(drp, dci, k, roots[i::p], seconds=secs)[:2]
+
+
+def cpu_baseline(rp_h, ci_h, k, order, secs):
+    """The oracle's run of the paper's method on the host's cores: Pre-Core,
+    Pre-List and the orientation once (single thread, timed separately),
+    then the listing from the roots (BitCol on the degeneracy DAG for the
+    color order, SDegree on the degree DAG otherwise), each worker process
+    taking every p-th root of one fixed random order for `secs` seconds."""
     global _CPU_JOB
     import multiprocessing as mp
     import numpy as np
+    import oracle
     try:
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
         ncpu = os.cpu_count() or 1
     procs = max(1, min(16, ncpu))
-    perm = np.random.default_rng(7).permutation(len(rp_h) - 1).astype(np.int32)
-    _CPU_JOB = (rp_h, ci_h, k, perm)
+    t = time.perf_counter()
+    removed = oracle.precore(rp_h, ci_h, k)
+    removed, pl, _, _ = oracle.prelist(rp_h, ci_h, k, removed)
+    if order == "color":
+        drp, dci, _, _ = oracle.degeneracy_dag(rp_h, ci_h, removed)
+    else:
+        drp, dci = oracle.degree_dag(rp_h, ci_h, removed)[:2]
+    prep_s = time.perf_counter() - t
+    roots = np.flatnonzero(np.diff(drp) >= k - 1).astype(np.int32)
+    roots = roots[np.random.default_rng(7).permutation(len(roots))]
+    _CPU_JOB = (drp, dci, k, roots)
+    worker = _cpu_worker if order == "color" else _cpu_worker_sdegree
     t = time.perf_counter()
     with mp.get_context("fork").Pool(procs) as pool:
-        res = pool.map(_cpu_worker, [(i, procs, secs) for i in range(procs)])
+        res = pool.map(worker, [(i, procs, secs) for i in range(procs)])
     el = time.perf_counter() - t
     c_cpu = sum(r[0] for r in res)
     done = sum(r[1] for r in res)
+    method = "BitCol on the degeneracy DAG" if order == "color" else "SDegree on the degree DAG"
     cpu = {"value": c_cpu / el, "unit": "k-cliques/s", "cores": procs, "kind": "oracle",
-           "sample": f"ordered-recursion oracle, {procs} processes over disjoint strided slices of one fixed random "
-                     f"root order, {secs:.0f}s each: {done} roots completed, {c_cpu} cliques counted in {el:.1f}s"}
+           "sample": f"the oracle's {method}, {procs} processes over disjoint strided slices of one fixed random "
+                     f"order of the {len(roots)} roots, {secs:.0f}s each: {done} roots completed, {c_cpu} cliques "
+                     f"counted in {el:.1f}s; its Pre-Core, Pre-List and orientation took {prep_s:.1f}s on one "
+                     f"core before the sample and are not in the rate"}
     log(f"cpu baseline: {cpu}")
     return cpu
 
@@ -133,6 +162,48 @@ def copy_calibration(mib: int):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def measured_peaks(torch):
+    """The three rates measured on this GPU by the microbenchmarks of
+    libkcpeaks.so: int32 VALU operations/s (AND, popcount-accumulate and a
+    three-input bit operation on 8 independent chains per lane, 8 waves per
+    SIMD), LDS bytes/s (conflict-free 16-byte reads), HBM bytes/s (a 1 GiB
+    device copy, read + write)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2203_13512_amd", "libkcpeaks.so")
+    if not os.path.exists(path):
+        log("libkcpeaks.so is missing: no measured peaks")
+        return None
+    L = ctypes.CDLL(path)
+    L.kcp_measure.restype = ctypes.c_int32
+    L.kcp_measure.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = cus * 8
+    scratch = torch.empty(blocks * 256, dtype=torch.int32, device="cuda:0")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    out = {}
+    for which, name, iters, reps, scale in ((0, "valu_int32_tops", 20000, 10, 1e12),
+                                            (1, "lds_tbps", 100000, 10, 1e12),
+                                            (2, "hbm_copy_gbps", 0, 10, 1e9)):
+        ms, units = ctypes.c_double(), ctypes.c_double()
+        st = L.kcp_measure(which, blocks, iters, reps, ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * 4,
+                           ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                           ctypes.byref(ms), ctypes.byref(units))
+        if st != 0:
+            log(f"peak microbenchmark {name} failed with status {st}")
+            return None
+        out[name] = round(units.value / (ms.value / 1e3) / scale, 3)
+    del scratch, src, dst
+    torch.cuda.empty_cache()
+    out["cus"] = cus
+    log(f"measured peaks: {out}")
+    return out
 
 
 SD_CLASSES = [64, 256, 1024, 4096, 16384, 65536]
@@ -176,12 +247,19 @@ def roofline_of(st_list, w_name, k, variant):
     alg_ops = 2.0 * st["class_work"][dom]
     achieved = alg_ops / dom_s / 1e12 if dom_s > 0 else 0.0
     pt = PROFILED_TRAFFIC
-    traffic = pt["bytes"] if (pt["sources_sha256_16"] == listing_sources_sha() and pt["word_class"] == W
-                              and pt["workload"] == w_name and pt["k"] == k and variant == "learned") else None
+    same = (pt["sources_sha256_16"] == listing_sources_sha() and pt["word_class"] == W
+            and pt["workload"] == w_name and pt["k"] == k and variant == "learned")
+    traffic = pt["bytes"] if same else None
+    # the algorithmic rate counts ceil(s/32) words for every BitJoin, also for
+    # the joins run on re-encoded one- and two-word rows; the instruction
+    # issue the profiler measured on the same launch is reported beside it
+    valu = (round(pt["valu_wave_insts"] / (pt["valu_launch_ms"] / 1e3) / VALU_ISSUE_PEAK_PER_S, 4)
+            if same else None)
     list_ms = statistics.fmean(s["list_ms"] for s in st_list)
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(INT32_VALU_PEAK_TOPS, 3),
             "unit": "TOP/s", "frac": round(achieved / INT32_VALU_PEAK_TOPS, 5), "traffic": traffic,
             "traffic_unit": "bytes per launch (HBM, profiler counters)",
+            "valu_issue_frac_measured": valu,
             "kernel": f"k_bitcol_list, {W}-word bitmaps", "launch_ms": round(cms[dom], 3),
             "launches_averaged": len(st_list),
             "algorithmic_words": int(st["class_work"][dom]), "tasks": int(st["class_tasks"][dom]),
@@ -192,6 +270,19 @@ def roofline_of(st_list, w_name, k, variant):
             "bitjoins_on_reencoded_rows": int(st["isect_compressed"]),
             # the listing phase as a whole (all classes, in sequence or overlapped)
             "chip_achieved": round(2.0 * st["work"] / (list_ms / 1e3) / 1e12, 4)}
+
+
+def with_measured_peak(roof, peaks):
+    """Adds the rate the microbenchmark reached on this GPU for the roofline's
+    bound and the achieved rate as a fraction of it (`peak` stays the
+    published figure)."""
+    if peaks:
+        key = {"alu": "valu_int32_tops", "hbm": "hbm_copy_gbps"}.get(roof["bound"])
+        if key and peaks.get(key):
+            roof["peak_measured"] = peaks[key]
+            roof["frac_of_measured"] = round(roof["achieved"] / peaks[key], 5)
+        roof["measured_peaks"] = peaks
+    return roof
 
 
 def main():
@@ -236,7 +327,7 @@ def main():
     log(f"workload {w.name}: n={len(rp_h) - 1} nnz={len(ci_h)} k={k} generated in {time.time() - t0:.1f}s")
     # the CPU baseline runs first, in worker processes forked before this
     # process touches the GPU
-    cpu = None if args.no_cpu else cpu_baseline(rp_h, ci_h, k, args.cpu_seconds)
+    cpu = None if args.no_cpu else cpu_baseline(rp_h, ci_h, k, args.order, args.cpu_seconds)
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(rp_h).to(dev)
     ci = torch.from_numpy(ci_h).to(dev)
@@ -257,6 +348,8 @@ def main():
             base["mlp"] = mlp
         kwargs[v] = base
         log(f"variant {v}: {({key: val for key, val in base.items() if key != 'mlp'})}")
+
+    peaks = measured_peaks(torch)
 
     # load the library's code objects (not a step: a tiny graph, untimed)
     prime = graphgen.erdos_renyi(200, 0.2, seed=1)
@@ -308,8 +401,8 @@ def main():
                               "steps": len(r["times"]), "n_tasks": r["stats"][-1]["n_tasks"],
                               "launch": {key: val for key, val in kwargs[v].items() if key != "mlp"}}
                           for v, r in done.items()},
-            "roofline": (roofline_of(R["stats"], w.name, k, head) if args.order == "color"
-                         else roofline_sdegree(R["stats"])),
+            "roofline": with_measured_peak(roofline_of(R["stats"], w.name, k, head) if args.order == "color"
+                                           else roofline_sdegree(R["stats"]), peaks),
             "cpu_baseline": cpu,
             # context only: the paper reports speedups of its methods over its
             # own CPU baselines (total serial time over its ten datasets), no rates

@@ -69,6 +69,8 @@ def _load():
         "orc_bitcol_encode": [i32, vp, vp, i32, vp, vp],
         "orc_bitcol_dag": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp],
         "orc_bitcol_roots": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp],
+        "orc_bitcol_roots_timed": [i32, vp, vp, i32, i32, i32, vp, dbl, vp, vp],
+        "orc_sdegree_roots_timed": [i32, vp, vp, i32, i32, vp, dbl, vp, vp],
         "orc_sdegree_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
         "orc_method_count": [i32, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -290,6 +292,34 @@ def bitcol_dag(drp, dci, k: int, L: int = 32):
     d["colors"] = colors[:n]
     d["edges"] = edges[:n]
     return int(c[0]), d
+
+
+def bitcol_count_roots(drp, dci, k: int, roots, seconds: float, L: int = 32):
+    """BitCol from `roots` of the DAG in order until `seconds` pass (a timing
+    sample).  Returns (count, roots_completed, finished)."""
+    drp, dci = _csr(drp, dci)
+    n = len(drp) - 1
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    c = np.zeros(1, dtype=np.uint64)
+    done = np.zeros(1, dtype=np.int32)
+    st = _load().orc_bitcol_roots_timed(n, _p(drp), _p(dci), k, L, len(r), _p(r), float(seconds), _p(c), _p(done))
+    if st not in (OK, EBUDGET):
+        _check(st, "bitcol_count_roots")
+    return int(c[0]), int(done[0]), st == OK
+
+
+def sdegree_count_roots(drp, dci, k: int, roots, seconds: float):
+    """SDegree from `roots` of the DAG in order until `seconds` pass (a timing
+    sample).  Returns (count, roots_completed, finished)."""
+    drp, dci = _csr(drp, dci)
+    n = len(drp) - 1
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    c = np.zeros(1, dtype=np.uint64)
+    done = np.zeros(1, dtype=np.int32)
+    st = _load().orc_sdegree_roots_timed(n, _p(drp), _p(dci), k, len(r), _p(r), float(seconds), _p(c), _p(done))
+    if st not in (OK, EBUDGET):
+        _check(st, "sdegree_count_roots")
+    return int(c[0]), int(done[0]), st == OK
 
 
 def bitcol_roots(drp, dci, k: int, roots, L: int = 32):

@@ -588,6 +588,7 @@ typedef struct {
   uint64_t count, nodes, isect, elems;
   int status;
   int noprune; /* ablation: no d+ <= l-2 skip, recurse into any non-empty C' */
+  double deadline; /* CLOCK_MONOTONIC seconds (0 = none) */
 } sdeg_t;
 
 static int32_t merge_join(const int32_t* a, int32_t na, const int32_t* b, int32_t nb, int32_t* out) {
@@ -615,6 +616,10 @@ static void sdegree_list(sdeg_t* S, int32_t l, const int32_t* C, int32_t nc, int
     int32_t m = merge_join(S->dcol + S->drp[u], du, C, nc, next);
     S->isect++;
     S->elems += (uint64_t)nc + (uint64_t)du;
+    if (S->deadline > 0.0 && (S->isect & 0xffff) == 0 && mono_now() > S->deadline) {
+      S->status = ORC_EBUDGET;
+      return;
+    }
     if (l == 2) {
       if (add_checked(&S->count, (uint64_t)m)) S->status = ORC_EOVERFLOW;
     } else if (S->noprune ? m > 0 : m > l - 2) {
@@ -751,6 +756,7 @@ typedef struct {
   uint64_t count, nodes, isect, words;
   int status;
   int noprune;           /* ablation: no color(v) < l skip */
+  double deadline;       /* CLOCK_MONOTONIC seconds (0 = none) */
 } bitcol_t;
 
 static int32_t bits_set(const uint32_t* x, int32_t nw) {
@@ -770,6 +776,10 @@ static void bitcol_list(bitcol_t* S, int32_t l, const uint32_t* CB, int32_t dept
     for (int32_t i = 0; i < S->nw; ++i) next[i] = Bv[i] & CB[i]; /* BitJoin */
     S->isect++;
     S->words += (uint64_t)((S->s + 31) / 32);
+    if (S->deadline > 0.0 && (S->isect & 0xffff) == 0 && mono_now() > S->deadline) {
+      S->status = ORC_EBUDGET;
+      return;
+    }
     int32_t p = bits_set(next, S->nw);
     if (l == 2) {
       if (add_checked(&S->count, (uint64_t)p)) S->status = ORC_EOVERFLOW;
@@ -830,6 +840,41 @@ static int bitcol_ws_init(bitcol_ws_t* w, int32_t n, const int32_t* drp, int32_t
   }
   for (int32_t v = 0; v < n; ++v) w->pos[v] = -1;
   return ORC_OK;
+}
+
+/* SDegree from roots[0..nroots) in that order until `seconds` have passed (a
+ * timing sample); outputs and status as orc_bitcol_roots_timed below. */
+int orc_sdegree_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t nroots,
+                            const int32_t* roots, double seconds, uint64_t* count, int32_t* roots_done) {
+  if (n < 0 || k < 3 || nroots < 0 || seconds <= 0.0) return ORC_EINVAL;
+  for (int32_t i = 0; i < nroots; ++i)
+    if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
+  *count = 0;
+  *roots_done = 0;
+  int32_t md = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (drp[u + 1] - drp[u] > md) md = drp[u + 1] - drp[u];
+  sdeg_t S;
+  memset(&S, 0, sizeof(S));
+  S.drp = drp;
+  S.dcol = dcol;
+  S.stride = md + 1;
+  S.deadline = mono_now() + seconds;
+  S.buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)S.stride * ((size_t)k + 2));
+  if (!S.buf) return ORC_ENOMEM;
+  for (int32_t i = 0; i < nroots && !S.status; ++i) {
+    int32_t u = roots[i];
+    int32_t du = drp[u + 1] - drp[u];
+    if (du >= k - 1) {
+      memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
+      sdegree_list(&S, k - 1, S.buf, du, 0);
+    }
+    if (!S.status) (*roots_done)++;
+    if (!S.status && mono_now() > S.deadline) S.status = ORC_EBUDGET;
+  }
+  free(S.buf);
+  *count = S.count;
+  return S.status;
 }
 
 /* BitCol (Alg. 6) from one root u of the DAG: builds G_u from N+(u), colors
@@ -942,6 +987,36 @@ int orc_bitcol_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t
     if (root_words) root_words[i] = S.words - w0;
   }
   bitcol_ws_free(&w);
+  return st;
+}
+
+/* BitCol from roots[0..nroots) in that order until `seconds` have passed (a
+ * timing sample): *count receives the cliques found, including those of a
+ * root cut short by the deadline, *roots_done the roots completed.  Returns
+ * ORC_EBUDGET when the deadline cut the run short. */
+int orc_bitcol_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t L,
+                           int32_t nroots, const int32_t* roots, double seconds, uint64_t* count,
+                           int32_t* roots_done) {
+  if (n < 0 || k < 3 || L < 1 || L > 32 || nroots < 0 || seconds <= 0.0) return ORC_EINVAL;
+  for (int32_t i = 0; i < nroots; ++i)
+    if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
+  *count = 0;
+  *roots_done = 0;
+  bitcol_ws_t w;
+  if (bitcol_ws_init(&w, n, drp, k, L)) return ORC_ENOMEM;
+  bitcol_t S;
+  memset(&S, 0, sizeof(S));
+  S.deadline = mono_now() + seconds;
+  int st = ORC_OK;
+  for (int32_t i = 0; i < nroots && !st; ++i) {
+    int32_t nc = 0;
+    int64_t ec = 0;
+    st = bitcol_root(&S, &w, drp, dcol, k, L, roots[i], &nc, &ec);
+    if (!st) (*roots_done)++;
+    if (!st && mono_now() > S.deadline) st = ORC_EBUDGET;
+  }
+  bitcol_ws_free(&w);
+  *count = S.count;
   return st;
 }
 

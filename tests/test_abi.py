@@ -24,6 +24,15 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_rate_microbenchmark_library_is_built():
+    """The benchmark's rate microbenchmarks live in a library of their own."""
+    path = os.path.join(os.path.dirname(kc.LIB_PATH), "libkcpeaks.so")
+    assert os.path.exists(path), "build the libraries first (__graft_entry__.build())"
+    lib = ctypes.CDLL(path)
+    assert hasattr(lib, "kcp_measure")
+    assert not hasattr(lib, "kclique_count")
+
+
 def test_status_strings_without_device():
     lib = kc._lib()
     for st in (0, -1, -2, -3, -4, -5, -6):

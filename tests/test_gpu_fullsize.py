@@ -8,8 +8,9 @@ sampled outputs the oracle computes one by one:
   - the orientation: every root's out-degree and core number equal the
     oracle's degeneracy DAG and peel levels (all 4M vertices);
   - Pre-List's count equals the oracle's;
-  - sampled roots: cliques listed from the root, BitJoins and words equal
-    the oracle's BitCol run from that root on its own DAG;
+  - sampled roots (the dense part, random ones, and roots of the 8-, 12-
+    and 16-word bitmap classes): cliques listed from the root, BitJoins and
+    words equal the oracle's BitCol run from that root on its own DAG;
   - the per-root attributions sum to the total.
 """
 import math
@@ -75,7 +76,16 @@ def test_full_size_bench_configuration_sampled_roots(bench_graph):
     rng = np.random.default_rng(2203)
     dense = roots[(core[roots] >= 100) & (dplus[roots] <= 45)]
     rest = roots[core[roots] < 100]
-    sample = np.concatenate([dense, rng.choice(rest, 40, replace=False)])
+    # and from each of the 8-, 12- and 16-word bitmap classes (out-degree in
+    # (128, 256], (256, 384], (384, 512]) the 8 roots of smallest core number
+    # (ties by id): the cheapest ones for the oracle, still listed by the
+    # wide kernels in the benchmark's launch configuration
+    wide = []
+    for lo, hi in ((128, 256), (256, 384), (384, 512)):
+        cls = roots[(dplus[roots] > lo) & (dplus[roots] <= hi)]
+        assert len(cls) >= 8, (lo, hi)
+        wide.append(cls[np.lexsort((cls, core[cls]))][:8])
+    sample = np.concatenate([dense, rng.choice(rest, 40, replace=False), *wide])
     assert len(dense) >= 50
     say("oracle BitCol on", len(sample), "sampled roots")
     per = oracle.bitcol_roots(drp, dci, k, sample)
@@ -85,6 +95,7 @@ def test_full_size_bench_configuration_sampled_roots(bench_graph):
     assert np.array_equal(lg["isect"][sample], per["isect"].astype(np.int64))
     assert np.array_equal(lg["work"][sample], per["words"].astype(np.int64))
     assert int(per["count"].sum()) > 10**7
+    assert int(per["count"][-8:].sum()) > 10**7  # the 16-word roots list cliques
 
 
 def _spearman(a, b):
@@ -98,9 +109,9 @@ def test_learned_schedule_gain(bench_graph):
     them on 256 CUs); the roots the network ranks on top must hold most of
     the logged work, far more than the top roots by the degree estimate
     log C(d+, k-1), and its ranking of the roots that do any work must be
-    closer to the logged one.  At the benchmark's k = 8 the learned schedule
-    then lists faster than the degree schedule at the same count (same
-    kernels, same launch shape)."""
+    closer to the logged one.  The learned schedule then lists faster than
+    the degree schedule (same kernels, classes launched in sequence for both,
+    each schedule with its own tuned launch shape; median of 5 runs each)."""
     w, rp_h, ci_h, rp, ci = bench_graph
     k = 7
     dev = rp.device
@@ -126,16 +137,20 @@ def test_learned_schedule_gain(bench_graph):
     assert share_mlp > 0.9 and share_mlp > share_deg + 0.2
     assert r_mlp > r_deg
 
-    k = 8
-    mlp = scheduler.load_model(dev, k)
-    tuned = autotune.lookup(rp_h, ci_h, k, "color")
-    times, counts = {}, {}
+    # timing at the same k: each schedule with its own tuned launch shape and
+    # the classes in sequence for both; the median of 5 listing phases
+    times = {}
     for sched in ("learned", "degree"):
-        kw = dict(schedule=sched, stats=True, **tuned)
+        kw = dict(schedule=sched, stats=True, class_streams=1)
+        kw.update({key: v for key, v in autotune.lookup(rp_h, ci_h, k, "color", schedule=sched).items()
+                   if key not in kw})
         if sched == "learned":
             kw["mlp"] = mlp
-        counts[sched], s2 = kc.count(rp, ci, k, "color", **kw)
-        times[sched] = s2["list_ms"]
-        say(sched, "listing", round(s2["list_ms"], 1), "ms")
-    assert counts["learned"] == counts["degree"]
+        runs = []
+        for _ in range(5):
+            c2, s2 = kc.count(rp, ci, k, "color", **kw)
+            assert c2 == c
+            runs.append(s2["list_ms"])
+        times[sched] = float(np.median(runs))
+        say(sched, "listing, median of 5:", round(times[sched], 1), "ms", [round(t, 1) for t in runs])
     assert times["learned"] < times["degree"]

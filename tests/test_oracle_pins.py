@@ -378,6 +378,34 @@ def test_bitcol_roots_matches_the_whole_dag_run():
         assert total == int(per["count"].sum())
 
 
+def test_timed_bitcol_sample_counts_what_the_roots_list():
+    """The time-bounded runs from a list of roots (the CPU baseline's sample;
+    BitCol and SDegree) count exactly the cliques of those roots when they
+    have time to finish,
+    and, with all roots, the definition's count minus Pre-List's; a deadline
+    that has passed stops it after the root in progress."""
+    g = graphgen.chung_lu(3000, 12.0, 2.1, 300.0, planted=[18, 12], seed=5)
+    k = 5
+    rem = oracle.precore(*g, k)
+    rem, pl, _, _ = oracle.prelist(*g, k, rem)
+    drp, dci, _, _ = oracle.degeneracy_dag(*g, rem)
+    roots = np.flatnonzero(np.diff(drp) >= k - 1)
+    c, done, finished = oracle.bitcol_count_roots(drp, dci, k, roots, 600.0)
+    assert finished and done == len(roots)
+    assert c + pl == oracle.count(*g, k)
+    some = roots[1::4]
+    c, done, finished = oracle.bitcol_count_roots(drp, dci, k, some, 600.0)
+    assert c == int(oracle.bitcol_roots(drp, dci, k, some)["count"].sum())
+    c, done, finished = oracle.bitcol_count_roots(drp, dci, k, roots, 1e-9)
+    assert not finished and done == 1
+    ddrp, ddci = oracle.degree_dag(*g, rem)
+    droots = np.flatnonzero(np.diff(ddrp) >= k - 1)
+    c, done, finished = oracle.sdegree_count_roots(ddrp, ddci, k, droots, 600.0)
+    assert finished and done == len(droots) and c + pl == oracle.count(*g, k)
+    c, done, finished = oracle.sdegree_count_roots(ddrp, ddci, k, droots, 1e-9)
+    assert not finished and done == 1
+
+
 def test_paper_bitcol_trace_on_the_encoded_example():
     """BitColList (Alg. 6) traced by hand on the local graph of Example 6 and
     Table 3, taken as G_u of one root u.
