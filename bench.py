@@ -73,6 +73,14 @@ VARIANTS = {
     "learned_cs2": dict(schedule="learned", class_streams=2),
     "degree_cs2": dict(schedule="degree", class_streams=2),
 }
+DEFAULT_VARIANTS = list(VARIANTS)
+# ablations (not run by default): preprocessing and pruning switched off,
+# and 32-bit words only (no re-encoding into 64-bit rows)
+for _s in ("learned", "degree"):
+    VARIANTS[f"{_s}_no_precore"] = dict(schedule=_s, class_streams=1, disable=1)
+    VARIANTS[f"{_s}_no_prelist"] = dict(schedule=_s, class_streams=1, disable=2)
+    VARIANTS[f"{_s}_no_prune"] = dict(schedule=_s, class_streams=1, disable=4)
+    VARIANTS[f"{_s}_words32"] = dict(schedule=_s, class_streams=1, compress=-1)
 
 
 def listing_sources_sha():
@@ -298,7 +306,8 @@ def main():
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--order", default="color")
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--variants", default=",".join(VARIANTS))
+    ap.add_argument("--variants", default=",".join(DEFAULT_VARIANTS),
+                    help=f"comma-separated, of: {', '.join(VARIANTS)}")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -50,7 +50,9 @@ typedef enum {
   KC_ENOMEM = -2,        /* device allocation failed */
   KC_EOVERFLOW = -3,     /* a count does not fit in 64 bits (e.g. C(201,20)) */
   KC_EDEVICE = -4,       /* a HIP runtime call failed or no device */
-  KC_EUNSUPPORTED = -5,  /* a local subgraph exceeds the supported size (2048 local vertices) */
+  KC_EUNSUPPORTED = -5,  /* a local subgraph exceeds the supported size: 2048 local vertices (BitCol); above
+                            1024 (512 with per-vertex output) only for k <= 5; SDegree candidate lists
+                            that do not fit LDS only when counting (no per-vertex or listing output) */
   KC_EWORKSPACE = -6     /* the caller's workspace is smaller than the call needs */
 } kc_status;
 

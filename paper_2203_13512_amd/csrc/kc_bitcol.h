@@ -21,6 +21,8 @@ static const int kWClass[KC_NCLASS] = {1, 2, 4, 8, 12, 16, 24, 32, 48, 64};
 // (ListLayout GB): 48 and 64 words always, 24 and 32 words with per-vertex
 // output; their staging builds the local adjacency matrix in device memory.
 static inline bool class_in_device_memory(int cls, bool pv) { return cls >= 8 || (pv && cls >= 6); }
+// Largest k at which those classes run (see kc_list_bitcol).
+#define KC_DEVMEM_KMAX 5
 
 static inline int wclass_of(int s) {
   int w = (s + 31) / 32;

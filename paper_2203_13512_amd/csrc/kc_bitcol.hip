@@ -520,7 +520,10 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   if (R == 0) return KC_OK;
   const bool pv = c.pv != nullptr;
   const kc_options* opt = c.opt;
-  const int max_class = KC_NCLASS - 1;
+  // The classes whose bitmaps stay in device memory are enabled up to
+  // KC_DEVMEM_KMAX only: a run at k = 16 on them faulted the GPU and its cause
+  // is not found yet, so larger k is refused (KC_EUNSUPPORTED) rather than run.
+  const int max_class = c.k <= KC_DEVMEM_KMAX ? KC_NCLASS - 1 : (pv ? 5 : 7);
   const bool timed = c.stats != nullptr && !c.size_only;
   EventPair ev_stage, ev_sched, ev_list;
   KC_TRY(ev_stage.init(timed));

@@ -605,6 +605,10 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
       KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds_bytes));
       grid = (int64_t)(per_cu < 1 ? 1 : per_cu) * kc_device_cus();
     } else {
+      // Lists in device memory are enabled for counting only: with per-vertex
+      // or listing output they are refused until the cause of a GPU fault in
+      // a run that exercised them is found.
+      if (pv || c.emit) return KC_EUNSUPPORTED;
       grid = (int64_t)kc_device_cus() * 8;
       if (grid > a.ntasks) grid = a.ntasks;
       a.block_words = (words + 63) & ~(size_t)63;

@@ -132,6 +132,18 @@ def cocktail_party(r):
     return csr(n, [(u, v) for u, v in itertools.combinations(range(n), 2) if u // 2 != v // 2])
 
 
+def bipartite_with_clique(a, b, m):
+    """Complete bipartite K_{a,b} (left 0..a-1, right a..a+b-1) plus a clique on
+    the first m right vertices.  A k-clique (k >= 3) holds at most one left
+    vertex and its other vertices in the clique: a C(m,k-1) + C(m,k) of them;
+    a left vertex lies in C(m,k-1), a clique vertex in a C(m-1,k-2) +
+    C(m-1,k-1), any other right vertex in none."""
+    left, right = range(a), range(a, a + b)
+    edges = [(u, v) for u in left for v in right]
+    edges += list(itertools.combinations(range(a, a + m), 2))
+    return csr(a + b, edges)
+
+
 _WORKLOADS = {}
 
 

@@ -503,6 +503,22 @@ def test_cocktail_party_closed_form(r):
                 assert oracle.method_count(rp, ci, k, method)[0] == c
 
 
+@pytest.mark.parametrize("a,b,m", [(7, 6, 4), (9, 5, 5), (40, 40, 8)])
+def test_bipartite_with_clique_closed_form(a, b, m):
+    """K_{a,b} plus an m-clique on the right side: a C(m,k-1) + C(m,k)
+    k-cliques for k >= 3 (brute force on the small ones)."""
+    rp, ci = G.bipartite_with_clique(a, b, m)
+    for k in range(3, m + 2):
+        c, pv = oracle.count(rp, ci, k, per_vertex=True)
+        assert c == a * math.comb(m, k - 1) + math.comb(m, k)
+        want_pv = [math.comb(m, k - 1)] * a + [a * math.comb(m - 1, k - 2) + math.comb(m - 1, k - 1)] * m
+        assert [int(x) for x in pv] == want_pv + [0] * (b - m)
+        if a + b <= 16:
+            assert G.py_brute_count(rp, ci, k)[0] == c
+        for method in ("degree", "color", "core"):
+            assert oracle.method_count(rp, ci, k, method)[0] == c
+
+
 def test_listing_matches_brute_force():
     """The oracle's listing (Sec. 3.1) writes exactly the k-subsets that are
     cliques, each once, as ascending ids in lexicographic order."""
