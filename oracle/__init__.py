@@ -65,6 +65,7 @@ def _load():
         "orc_degree_dag": [i32, vp, vp, vp, vp, vp],
         "orc_degeneracy_dag": [i32, vp, vp, vp, vp, vp, vp, vp],
         "orc_sdegree_dag": [i32, vp, vp, i32, vp, vp, vp, vp, vp],
+        "orc_sdegree_reduced_dag": [i32, vp, vp, i32, vp, vp, vp, vp, vp],
         "orc_greedy_color": [i32, vp, vp, vp, vp],
         "orc_bitcol_encode": [i32, vp, vp, i32, vp, vp],
         "orc_bitcol_dag": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp],
@@ -72,6 +73,7 @@ def _load():
         "orc_bitcol_roots_timed": [i32, vp, vp, i32, i32, i32, vp, dbl, vp, vp],
         "orc_sdegree_roots_timed": [i32, vp, vp, i32, i32, vp, dbl, vp, vp],
         "orc_sdegree_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
+        "orc_sdegree_reduced_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
         "orc_method_count": [i32, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
     }
@@ -236,16 +238,19 @@ def merge_join(a, b) -> np.ndarray:
     return out[:m]
 
 
-def sdegree_dag(drp, dci, k: int):
+def sdegree_dag(drp, dci, k: int, reduce: bool = False):
+    """SDegree (Alg. 5) from every root of the DAG; with `reduce`, on each
+    root's induced DAG G_u (the out-neighbour reduction of Sec. 7.2)."""
     drp, dci = _csr(drp, dci)
     n = len(drp) - 1
     c = np.zeros(1, dtype=np.uint64)
     arrs = [np.zeros(max(n, 1), dtype=np.uint64) for _ in range(4)]
-    _check(_load().orc_sdegree_dag(n, _p(drp), _p(dci), k, _p(c), *[_p(a) for a in arrs]), "sdegree_dag")
+    fn = _load().orc_sdegree_reduced_dag if reduce else _load().orc_sdegree_dag
+    _check(fn(n, _p(drp), _p(dci), k, _p(c), *[_p(a) for a in arrs]), "sdegree_dag")
     return int(c[0]), dict(zip(["count", "nodes", "isect", "elems"], [a[:n] for a in arrs]))
 
 
-def sdegree_roots(drp, dci, k: int, roots):
+def sdegree_roots(drp, dci, k: int, roots, reduce: bool = False):
     """SDegree from the listed roots of the DAG only; dict of per-root arrays
     (count, nodes, isect, elems) in the order of `roots`."""
     drp, dci = _csr(drp, dci)
@@ -253,8 +258,8 @@ def sdegree_roots(drp, dci, k: int, roots):
     roots = np.ascontiguousarray(roots, dtype=np.int32)
     r = max(len(roots), 1)
     u = [np.zeros(r, dtype=np.uint64) for _ in range(4)]
-    _check(_load().orc_sdegree_roots(n, _p(drp), _p(dci), k, len(roots), _p(roots), *[_p(a) for a in u]),
-           "sdegree_roots")
+    fn = _load().orc_sdegree_reduced_roots if reduce else _load().orc_sdegree_roots
+    _check(fn(n, _p(drp), _p(dci), k, len(roots), _p(roots), *[_p(a) for a in u]), "sdegree_roots")
     return dict(zip(["count", "nodes", "isect", "elems"], [a[:len(roots)] for a in u]))
 
 
@@ -337,12 +342,13 @@ def bitcol_roots(drp, dci, k: int, roots, L: int = 32):
 
 def method_count(rp, ci, k: int, method: str, L: int = 32, disable: int = 0):
     """Whole SDegree ('degree'), BitCol ('color') or SDegree-on-degeneracy
-    ('core') pipeline as the paper orders it; `disable` skips Pre-Core (1),
+    ('core') pipeline as the paper orders it ('degree_reduced' and
+    'core_reduced': SDegree with the out-neighbour reduction of Sec. 7.2); `disable` skips Pre-Core (1),
     Pre-List (2) or the pruning (4).  Returns (total, prelist_count,
     per_root dict)."""
     rp, ci = _csr(rp, ci)
     n = len(rp) - 1
-    m = {"degree": 0, "color": 1, "core": 2}[method]
+    m = {"degree": 0, "color": 1, "core": 2, "degree_reduced": 3, "core_reduced": 4}[method]
     c = np.zeros(1, dtype=np.uint64)
     pl = np.zeros(1, dtype=np.uint64)
     u = [np.zeros(max(n, 1), dtype=np.uint64) for _ in range(4)]

@@ -628,18 +628,69 @@ static void sdegree_list(sdeg_t* S, int32_t l, const int32_t* C, int32_t nc, int
   }
 }
 
+/* SDegree from root u with the out-neighbour reduction of Sec. 7.2: the
+ * recursion runs on the DAG G_u induced by N+(u), whose vertices are the
+ * positions 0..s-1 of N+(u) and whose out-lists are L_i = N+(x_i) restricted
+ * to N+(u) (x_i = N+(u)[i]).  Alg. 5 then runs unchanged on G_u from the top
+ * call C = all of G_u: its joins are L_x with C, its pruning uses the
+ * out-degree |L_x| in G_u, and Lemma 2's cost of a join is |C| + |L_x|. */
+static int sdegree_reduced_root(sdeg_t* S, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t u) {
+  const int32_t s = drp[u + 1] - drp[u];
+  if (s < k - 1) return ORC_OK;
+  const int32_t* ids = dcol + drp[u];
+  size_t cap = 0;
+  for (int32_t i = 0; i < s; ++i) {
+    const int32_t d = drp[ids[i] + 1] - drp[ids[i]];
+    cap += (size_t)(d < s ? d : s);
+  }
+  int32_t* lrp = (int32_t*)malloc(sizeof(int32_t) * ((size_t)s + 1));
+  int32_t* lcol = (int32_t*)malloc(sizeof(int32_t) * (cap + 1));
+  if (!lrp || !lcol) { free(lrp); free(lcol); return ORC_ENOMEM; }
+  lrp[0] = 0;
+  for (int32_t i = 0; i < s; ++i) {
+    /* L_i: positions j with ids[j] in N+(x_i); both lists ascend by id */
+    const int32_t x = ids[i];
+    int32_t a = drp[x], ae = drp[x + 1], j = 0, o = lrp[i];
+    while (a < ae && j < s) {
+      if (dcol[a] == ids[j]) { lcol[o++] = j; a++; j++; }
+      else if (dcol[a] < ids[j]) a++;
+      else j++;
+    }
+    lrp[i + 1] = o;
+  }
+  const int32_t* save_rp = S->drp;
+  const int32_t* save_col = S->dcol;
+  S->drp = lrp;
+  S->dcol = lcol;
+  for (int32_t i = 0; i < s; ++i) S->buf[i] = i;
+  sdegree_list(S, k - 1, S->buf, s, 0);
+  S->drp = save_rp;
+  S->dcol = save_col;
+  free(lrp);
+  free(lcol);
+  return ORC_OK;
+}
+
 /* SDegree on a DAG.  Per root u (index = vertex id) the arrays receive the
  * cliques found from u and the work counters (any may be NULL).  k >= 3. */
-static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, uint64_t* count,
-                       uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems);
+static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, int reduce,
+                       uint64_t* count, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                       uint64_t* root_elems);
 
 int orc_sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, uint64_t* count,
                     uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
-  return sdegree_dag(n, drp, dcol, k, 0, count, root_count, root_nodes, root_isect, root_elems);
+  return sdegree_dag(n, drp, dcol, k, 0, 0, count, root_count, root_nodes, root_isect, root_elems);
 }
 
-static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, uint64_t* count,
-                       uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
+/* The same with the out-neighbour reduction (Sec. 7.2) on every root. */
+int orc_sdegree_reduced_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, uint64_t* count,
+                            uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_elems) {
+  return sdegree_dag(n, drp, dcol, k, 0, 1, count, root_count, root_nodes, root_isect, root_elems);
+}
+
+static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int noprune, int reduce,
+                       uint64_t* count, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                       uint64_t* root_elems) {
   if (n < 0 || k < 3) return ORC_EINVAL;
   *count = 0;
   int32_t md = 0;
@@ -656,7 +707,10 @@ static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32
   for (int32_t u = 0; u < n && !S.status; ++u) {
     int32_t du = drp[u + 1] - drp[u];
     uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, e0 = S.elems;
-    if (du >= k - 1) {
+    if (reduce) {
+      const int st = sdegree_reduced_root(&S, drp, dcol, k, u);
+      if (st) { free(S.buf); return st; }
+    } else if (du >= k - 1) {
       memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
       sdegree_list(&S, k - 1, S.buf, du, 0);
     }
@@ -673,9 +727,25 @@ static int sdegree_dag(int32_t n, const int32_t* drp, const int32_t* dcol, int32
 
 /* The same for a list of roots only (sampled or sliced runs on large graphs):
  * entry i of each output describes roots[i]. */
+static int sdegree_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int reduce, int32_t nroots,
+                         const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                         uint64_t* root_elems);
+
 int orc_sdegree_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t nroots,
                       const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
                       uint64_t* root_elems) {
+  return sdegree_roots(n, drp, dcol, k, 0, nroots, roots, root_count, root_nodes, root_isect, root_elems);
+}
+
+int orc_sdegree_reduced_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t nroots,
+                              const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes,
+                              uint64_t* root_isect, uint64_t* root_elems) {
+  return sdegree_roots(n, drp, dcol, k, 1, nroots, roots, root_count, root_nodes, root_isect, root_elems);
+}
+
+static int sdegree_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int reduce, int32_t nroots,
+                         const int32_t* roots, uint64_t* root_count, uint64_t* root_nodes, uint64_t* root_isect,
+                         uint64_t* root_elems) {
   if (n < 0 || k < 3 || nroots < 0) return ORC_EINVAL;
   for (int32_t i = 0; i < nroots; ++i)
     if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
@@ -693,7 +763,10 @@ int orc_sdegree_roots(int32_t n, const int32_t* drp, const int32_t* dcol, int32_
     int32_t u = roots[i];
     int32_t du = drp[u + 1] - drp[u];
     uint64_t c0 = S.count, n0 = S.nodes, i0 = S.isect, e0 = S.elems;
-    if (du >= k - 1) {
+    if (reduce) {
+      const int st = sdegree_reduced_root(&S, drp, dcol, k, u);
+      if (st) { free(S.buf); return st; }
+    } else if (du >= k - 1) {
       memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
       sdegree_list(&S, k - 1, S.buf, du, 0);
     }
@@ -1023,7 +1096,8 @@ int orc_bitcol_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, i
 /* ------------------------------------------- whole methods (Alg. 5, 6) */
 /* Pre-Core, Pre-List, orientation and listing, as the paper orders them.
  * method 0 = SDegree (degree DAG), 1 = BitCol (degeneracy DAG, L bits),
- * 2 = SDegree on the degeneracy DAG (Sec. 6.2: any vertex order).
+ * 2 = SDegree on the degeneracy DAG (Sec. 6.2: any vertex order), 3 and 4 =
+ * methods 0 and 2 with the out-neighbour reduction (Sec. 7.2).
  * disable: ablation bits 1 = skip Pre-Core, 2 = skip Pre-List, 4 = no
  * pruning (SDegree: no d+ <= l-2 skip, children with any member entered;
  * BitCol: no color(v) < l skip).  Returns the total count (Pre-List cliques
@@ -1033,7 +1107,7 @@ int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k
                      int32_t disable, uint64_t* count, uint64_t* prelist_count, uint64_t* root_count,
                      uint64_t* root_nodes, uint64_t* root_isect, uint64_t* root_work, int32_t* root_dplus,
                      int32_t* root_core, int32_t* root_colors, int64_t* root_edges) {
-  if (n < 0 || k < 3 || method < 0 || method > 2) return ORC_EINVAL;
+  if (n < 0 || k < 3 || method < 0 || method > 4) return ORC_EINVAL;
   *count = 0;
   if (prelist_count) *prelist_count = 0;
   if (n == 0) return ORC_OK;
@@ -1048,7 +1122,7 @@ int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k
   uint64_t pl = 0;
   if (!st && !(disable & 2)) st = orc_prelist(n, rp, col, k, removed, &pl, NULL, NULL);
   if (!st) {
-    if (method == 0) st = orc_degree_dag(n, rp, col, removed, drp, dcol);
+    if (method == 0 || method == 3) st = orc_degree_dag(n, rp, col, removed, drp, dcol);
     else st = orc_degeneracy_dag(n, rp, col, removed, drp, dcol, NULL, core);
   }
   uint64_t c = 0;
@@ -1057,12 +1131,12 @@ int orc_method_count(int32_t n, const int32_t* rp, const int32_t* col, int32_t k
     if (method == 1)
       st = bitcol_dag(n, drp, dcol, k, L, noprune, &c, root_count, root_nodes, root_isect, root_work, root_colors,
                       root_edges);
-    else st = sdegree_dag(n, drp, dcol, k, noprune, &c, root_count, root_nodes, root_isect, root_work);
+    else st = sdegree_dag(n, drp, dcol, k, noprune, method >= 3, &c, root_count, root_nodes, root_isect, root_work);
   }
   if (!st) {
     if (root_dplus)
       for (int32_t u = 0; u < n; ++u) root_dplus[u] = drp[u + 1] - drp[u];
-    if (root_core && method != 0) memcpy(root_core, core, sizeof(int32_t) * (size_t)n);
+    if (root_core && method != 0 && method != 3) memcpy(root_core, core, sizeof(int32_t) * (size_t)n);
     if (add_checked(&c, pl)) st = ORC_EOVERFLOW;
   }
   if (!st) {

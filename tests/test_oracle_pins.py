@@ -542,6 +542,55 @@ def test_listing_matches_brute_force():
     assert total == 3 and [tuple(int(x) for x in r) for r in rows] == [(0, 1, 2, 3), (0, 1, 3, 5), (8, 9, 10, 11)]
 
 
+def test_reduced_sdegree_trace_on_the_encoded_example():
+    """SDegree with the out-neighbour reduction (Sec. 7.2) on the graph H of
+    Table 3 (edges 1-2 1-3 1-4 1-5 1-6 2-3 2-4 2-6 3-4 3-5 4-6 5-6), k = 4,
+    traced by hand.  Degree order (d, id): v5 < v2 < v3 < v4 < v6 < v1, so
+    N+(v2) = {v1,v3,v4,v6}, N+(v3) = {v1,v4}, N+(v4) = {v1,v6},
+    N+(v5) = {v1,v3,v6}, N+(v6) = {v1}; the roots (d+ >= 3) are v2 and v5.
+    Root v2, local positions v1,v3,v4,v6 = 0..3, reduced lists L0 = {},
+    L1 = {0,2}, L2 = {0,3}, L3 = {0}; top call l = 3, |C| = 4:
+      x=0 skipped (|L| = 0 <= 1); x=1 joins (4+2) -> {0,2}, node at l = 2:
+        x=0 skipped, x=2 joins (2+2) -> {0}: 1 clique;
+      x=2 joins (4+2) -> {0,3}, node at l = 2: x=0 skipped, x=3 joins
+        (2+1) -> {0}: 1 clique;  x=3 skipped (|L| = 1 <= 1).
+      2 cliques, 4 joins, work 6+4+6+3 = 19, 3 nodes (as without reduction).
+    Root v5, positions v1,v3,v6, L0 = {}, L1 = {0} (v4 is not in N+(v5)),
+    L2 = {0}: every candidate is skipped (|L| <= 1): 0 joins, 1 node.
+    Without the reduction v3 keeps d+ = 2 and joins once (3+2 = 5 elements)."""
+    E = [(1, 2), (1, 3), (1, 4), (1, 5), (1, 6), (2, 3), (2, 4), (2, 6), (3, 4), (3, 5), (4, 6), (5, 6)]
+    g = G.csr(6, [(a - 1, b - 1) for a, b in E])
+    want = {"count": [0, 2, 0, 0, 0, 0], "isect": [0, 4, 0, 0, 0, 0], "work": [0, 19, 0, 0, 0, 0],
+            "nodes": [0, 3, 0, 0, 1, 0]}
+    c, pl, per = oracle.method_count(*g, 4, "degree_reduced")
+    assert c == 2 and pl == 0
+    for key, v in want.items():
+        assert [int(x) for x in per[key]] == v, key
+    c, pl, per = oracle.method_count(*g, 4, "degree")
+    assert [int(x) for x in per["isect"]] == [0, 4, 0, 0, 1, 0]
+    assert [int(x) for x in per["work"]] == [0, 19, 0, 0, 5, 0]
+
+
+def test_reduced_sdegree_never_joins_more():
+    """The reduction only shortens out-lists (L_x is N+(x) restricted to
+    N+(u)): per root, the same nodes, no more joins and no more Lemma-2
+    elements than without it; the counts agree root by root."""
+    g = graphgen.chung_lu(3000, 12.0, 2.1, 300.0, planted=[18, 12], seed=9)
+    for k in (3, 4, 5, 6):
+        a = oracle.method_count(*g, k, "degree")[2]
+        b = oracle.method_count(*g, k, "degree_reduced")[2]
+        assert np.array_equal(a["count"], b["count"]) and np.array_equal(a["nodes"], b["nodes"])
+        assert np.all(b["isect"] <= a["isect"]) and np.all(b["work"] <= a["work"])
+        assert b["work"].sum() < a["work"].sum()
+        rem = oracle.precore(*g, k)
+        rem, _, _, _ = oracle.prelist(*g, k, rem)
+        drp, dci = oracle.degree_dag(*g, rem)
+        roots = np.flatnonzero(np.diff(drp) >= k - 1)[::5]
+        sub = oracle.sdegree_roots(drp, dci, k, roots, reduce=True)
+        for key, kk in (("count", "count"), ("isect", "isect"), ("elems", "work"), ("nodes", "nodes")):
+            assert np.array_equal(sub[key], b[kk][roots]), key
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_ablations_and_orders_reach_the_definition(seed):
     """SDegree on the degree or the degeneracy order (Sec. 6.2: any order
@@ -557,7 +606,7 @@ def test_ablations_and_orders_reach_the_definition(seed):
         core = oracle.core_numbers(rp, ci)
         for k in (3, 4, 5):
             want = oracle.count(rp, ci, k)
-            for method in ("degree", "core", "color"):
+            for method in ("degree", "core", "color", "degree_reduced", "core_reduced"):
                 base = oracle.method_count(rp, ci, k, method)
                 assert base[0] == want
                 for disable in (1, 2, 4, 7):
@@ -565,6 +614,6 @@ def test_ablations_and_orders_reach_the_definition(seed):
                     assert got[0] == want, (method, disable)
                     if disable & 4:
                         assert got[2]["isect"].sum() >= base[2]["isect"].sum()
-                if method == "core":
+                if method in ("core", "core_reduced"):
                     d = base[2]["dplus"]
                     assert np.all(d <= np.maximum(core, 0))
