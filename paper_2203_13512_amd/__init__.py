@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libkclique.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "kclique.h")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
-ORDERS = {"degree": 0, "color": 1, "core": 2}
+ORDERS = {"degree": 0, "color": 1, "core": 2, "degree_reduced": 3, "core_reduced": 4}
 NO_PRECORE, NO_PRELIST, NO_PRUNE = 1, 2, 4
 SCHEDULES = {"degree": 0, "learned": 1}
 MLP_IN, MLP_HIDDEN = 4, 64

@@ -126,7 +126,11 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   const kc_options* opt = opt_in ? opt_in : &defaults;
   if (n < 0 || k < 1 || !count_out) return KC_EINVAL;
   if (cap && (!ext_scr || order != KC_ORDER_COLOR || pv_out)) return KC_EUNSUPPORTED;
-  if (order != KC_ORDER_DEGREE && order != KC_ORDER_COLOR && order != KC_ORDER_CORE) return KC_EINVAL;
+  if (order < KC_ORDER_DEGREE || order > KC_ORDER_CORE_REDUCED) return KC_EINVAL;
+  // the reduced SDegree orders orient the graph as their base order does
+  const bool reduce = order == KC_ORDER_DEGREE_REDUCED || order == KC_ORDER_CORE_REDUCED;
+  if (order == KC_ORDER_DEGREE_REDUCED) order = KC_ORDER_DEGREE;
+  if (order == KC_ORDER_CORE_REDUCED) order = KC_ORDER_CORE;
   if (opt->disable & ~(KC_NO_PRECORE | KC_NO_PRELIST | KC_NO_PRUNE)) return KC_EINVAL;
   if (opt->schedule != KC_SCHED_DEGREE && opt->schedule != KC_SCHED_LEARNED) return KC_EINVAL;
   if (n > 0 && !row_ptr) return KC_EINVAL;
@@ -287,6 +291,7 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     c.capture = cap;
     c.size_only = size_out != nullptr;
     c.emit = listing ? &em : nullptr;
+    c.reduce = reduce;
     KC_TRY(ev.record(2, s));
     if (order == KC_ORDER_COLOR) KC_TRY(kc_list_bitcol(c, scr, s));
     else KC_TRY(kc_list_sdegree(c, scr, s));

@@ -199,6 +199,7 @@ struct kc_list_ctx {
   struct kc_capture* capture;  // non-null: prepare only, hand the listing phase over
   bool size_only;              // stop before the listing launches (workspace size query)
   const kc_emit* emit;         // non-null: write every clique listed (no schedule, no per-vertex output)
+  bool reduce;                 // SDegree: out-neighbour reduction (Sec. 7.2)
 };
 
 // A prepared call's listing phase, to be captured into a HIP graph and

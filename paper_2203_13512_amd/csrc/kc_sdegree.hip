@@ -68,6 +68,8 @@ struct SdArgs {
   int* flags;
   kc_emit e;              // listing output (EMIT instances)
   int noprune;            // ablation: no d+ <= l-2 skip; a child with any member is entered
+  uint16_t* pool;         // out-neighbour reduction: per-workgroup pool of reduced lists
+  int64_t pool_cap;       // its entries per workgroup
 };
 
 // Memory of one workgroup (words): list[K][SMAX] | lidx[K][SMAX] (per-vertex)
@@ -350,6 +352,312 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   }
 }
 
+
+// ---- SDegree with the out-neighbour reduction (Sec. 7.2) ----------------
+// The recursion of a work item runs on the DAG G_u induced by N+(u): vertex i
+// of G_u is position i of N+(u) (ascending ids, in LDS) and its out-list is
+// L_i = {j : N+(u)[j] in N+(x_i)}, stored as 16-bit positions in a
+// per-workgroup pool in device memory.  A whole-root item stages every L_i;
+// an edge item (u, x) stages L_x and the lists of its members (every deeper
+// candidate set lies inside L_x).  Staging is flattened over 64 candidates as
+// the level-2 joins are: each candidate's range of N+(x_i) inside
+// [min N+(u), max N+(u)] is found, the ranges are laid end to end, each lane
+// takes one entry and finds it in N+(u) by binary search, and the hits are
+// compacted in entry order, so each list's members stay together.
+// The candidate sets of the recursion are position lists, each with a bitmap
+// (LDS); a join of L_x with C is one bitmap test per entry of L_x.  The sets
+// are kept in the order their members are found (neither the counts nor the
+// logged work depend on it).  Pruning and work follow Alg. 5 on G_u: x is
+// skipped when |L_x| <= l-2 and a join costs |C| + |L_x| (Lemma 2 on G_u).
+
+// LDS of a reduced-SDegree workgroup (32-bit words): ids[SM] | lst[SM] |
+// lln[SM] | clist[K][SM] u16 | bm[K][SM/32] | cur[K] | size[K] | tot[K] u64
+static size_t sdr_words(int k, int smax) {
+  const size_t K = (size_t)k, S = (size_t)smax;
+  return 3 * S + K * S / 2 + K * (S / 32) + 4 * K + 8;
+}
+
+// Stages the reduced lists of the candidates cand[0..nc) (positions of
+// N+(u)) into the pool from `top`, and records where each one starts.
+__device__ void sdr_stage(const SdArgs& a, const int32_t* ids, int s, const uint16_t* cand, int nc,
+                          int32_t* lst, int32_t* lln, uint16_t* pool, int64_t& top, int lane, int32_t* fl_lo,
+                          int32_t* fl_off, int32_t* fl_cnt) {
+  const int32_t vmin = ids[0], vmax = ids[s - 1];
+  for (int b = 0; b < nc; b += 64) {
+    const int idx = b + lane;
+    int lo = 0, len = 0, ci = -1;
+    if (idx < nc) {
+      ci = cand[idx];
+      const int32_t x = ids[ci];
+      const int32_t xb = a.drp[x], xe = a.drp[x + 1];
+      int l0 = xb, h0 = xe;
+      while (l0 < h0) {
+        const int mid = (l0 + h0) >> 1;
+        if (a.dcol[mid] < vmin) l0 = mid + 1; else h0 = mid;
+      }
+      int l1 = l0, h1 = xe;
+      while (l1 < h1) {
+        const int mid = (l1 + h1) >> 1;
+        if (a.dcol[mid] <= vmax) l1 = mid + 1; else h1 = mid;
+      }
+      lo = l0;
+      len = l1 - l0;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    fl_lo[lane] = lo;
+    fl_off[lane] = incl - len;
+    if (lane == 63) fl_off[64] = incl;
+    fl_cnt[lane] = 0;
+    kc_wave_lds_sync();
+    int64_t base = top;
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      int q = -1, seg = 0;
+      if (t < total) {
+        int p0 = 0, p1 = 65;
+        while (p0 < p1) {
+          const int mid = (p0 + p1) >> 1;
+          if (fl_off[mid] <= t) p0 = mid + 1; else p1 = mid;
+        }
+        seg = p0 - 1;
+        const int32_t y = a.dcol[fl_lo[seg] + (t - fl_off[seg])];
+        const int r = sd_lower_bound(ids, 0, s, y);
+        if (r < s && ids[r] == y) q = r;
+      }
+      const bool hit = q >= 0;
+      const uint64_t mk = kc_ballot(hit);
+      if (hit) {
+        const int64_t o = base + kc_mbcnt(mk);
+        if (o < a.pool_cap) pool[o] = (uint16_t)q;  // the bound holds for a simple graph
+        atomicAdd(&fl_cnt[seg], 1);
+      }
+      base += __popcll(mk);
+    }
+    kc_wave_lds_sync();
+    const int cnt = fl_cnt[lane];
+    int inc2 = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc2, o, 64);
+      if (lane >= o) inc2 += y;
+    }
+    if (idx < nc) {
+      lst[ci] = (int32_t)(top + inc2 - cnt);
+      lln[ci] = cnt;
+    }
+    top = base;
+    kc_wave_lds_sync();
+  }
+}
+
+__device__ __forceinline__ bool sdr_bit(const uint32_t* bm, int e) { return (bm[e >> 5] >> (e & 31)) & 1u; }
+
+__global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int K = a.k;
+  const int SM = a.SMAX;
+  const int SMW = SM >> 5;
+  int32_t* ids = (int32_t*)lds;
+  int32_t* lst = ids + SM;
+  int32_t* lln = lst + SM;
+  uint16_t* clist = (uint16_t*)(lln + SM);
+  uint32_t* bm = (uint32_t*)(clist + (size_t)K * SM);
+  int32_t* cur = (int32_t*)(bm + (size_t)K * SMW);
+  int32_t* size = cur + K;
+  unsigned long long* tot = (unsigned long long*)(((uintptr_t)(size + K) + 7) & ~(uintptr_t)7);
+  uint16_t* pool = a.pool + (size_t)blockIdx.x * (size_t)a.pool_cap;
+  const int lane = threadIdx.x;
+  __shared__ int32_t sh_task[2];
+  __shared__ int32_t fl_lo[64], fl_off[65], fl_cnt[64];
+
+  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;
+  for (;;) {
+    if (lane == 0) {
+      unsigned long long t = atomicAdd(a.head, (unsigned long long)a.chunk);
+      sh_task[0] = (int32_t)(t < (unsigned long long)a.ntasks ? t : a.ntasks);
+      long long e = (long long)t + a.chunk;
+      sh_task[1] = (int32_t)(e < a.ntasks ? e : a.ntasks);
+    }
+    __syncthreads();
+    const int32_t t_lo = sh_task[0], t_hi = sh_task[1];
+    __syncthreads();
+    if (t_lo >= t_hi) break;
+    for (int32_t ti = t_lo; ti < t_hi; ++ti) {
+      const uint64_t task = a.tasks[ti];
+      const int32_t r = (int32_t)(task >> 32);
+      const int32_t xp1 = (int32_t)(uint32_t)task;  // 0: the whole root
+      const int32_t u = a.roots[r];
+      const int32_t b0 = a.drp[u];
+      const int32_t s0 = a.drp[u + 1] - b0;
+      const int kt = kc_vk(a.vk, u, a.k);
+      for (int i = lane; i < s0; i += 64) {
+        ids[i] = a.dcol[b0 + i];
+        lst[i] = -1;
+        lln[i] = 0;
+        clist[i] = (uint16_t)i;  // level 0: every position
+      }
+      for (int w = lane; w < SMW; w += 64) {
+        const int lo = w * 32;
+        bm[w] = lo >= s0 ? 0u : (s0 - lo >= 32 ? ~0u : ((1u << (s0 - lo)) - 1u));
+      }
+      __syncthreads();
+      // the lists this item can join
+      int64_t top = 0;
+      if (xp1) {
+        const uint16_t x0 = (uint16_t)(xp1 - 1);
+        clist[SM] = x0;  // a one-entry candidate list (level 1's list is rebuilt below)
+        kc_wave_lds_sync();
+        sdr_stage(a, ids, s0, clist + SM, 1, lst, lln, pool, top, lane, fl_lo, fl_off, fl_cnt);
+        __syncthreads();
+        const int n0 = top > a.pool_cap ? 0 : lln[x0];
+        const uint16_t* l0 = pool + lst[x0];
+        sdr_stage(a, ids, s0, l0, n0, lst, lln, pool, top, lane, fl_lo, fl_off, fl_cnt);
+      } else {
+        sdr_stage(a, ids, s0, clist, s0, lst, lln, pool, top, lane, fl_lo, fl_off, fl_cnt);
+      }
+      __syncthreads();
+      if (top > a.pool_cap) {
+        if (lane == 0) atomicOr(a.flags, KC_FLAG_TOOBIG);
+        continue;
+      }
+      const int end0 = xp1 ? xp1 : s0;
+      if (lane == 0) {
+        cur[0] = xp1 ? xp1 - 1 : 0;
+        size[0] = s0;
+        tot[0] = 0;
+      }
+      __syncthreads();
+      my_nodes += (lane == 0 && !xp1);
+      const int L0 = kt - 1;
+      int d = 0;
+      for (;;) {
+        const int l = L0 - d;
+        const int sz = size[d];
+        const int c = cur[d];
+        const int end = d == 0 ? end0 : sz;
+        if (c >= end) {
+          if (d == 0) break;
+          const unsigned long long T = tot[d];
+          if (lane == 0) tot[d - 1] += T;
+          kc_wave_lds_sync();
+          d--;
+          continue;
+        }
+        const uint16_t* C = clist + (size_t)d * SM;
+        const uint32_t* B = bm + (size_t)d * SMW;
+        if (l == 2) {
+          // a level-2 node: the entries of its candidates' lists laid end to
+          // end, one bitmap test each
+          uint32_t hits = 0;
+          for (int b = c; b < end; b += 64) {
+            const int idx = b + lane;
+            int lo = 0, len = 0;
+            if (idx < end) {
+              const int x = C[idx];
+              const int nx = lln[x];
+              if (nx > 0 || a.noprune) {
+                my_isect++;
+                my_work += (uint64_t)sz + (uint64_t)nx;
+                lo = lst[x];
+                len = nx;
+              }
+            }
+            int incl = len;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+              const int y = __shfl_up(incl, o, 64);
+              if (lane >= o) incl += y;
+            }
+            const int total_len = __shfl(incl, 63, 64);
+            fl_lo[lane] = lo;
+            fl_off[lane] = incl - len;
+            if (lane == 63) fl_off[64] = incl;
+            kc_wave_lds_sync();
+            for (int t = lane; t < total_len; t += 64) {
+              int p0 = 0, p1 = 65;
+              while (p0 < p1) {
+                const int mid = (p0 + p1) >> 1;
+                if (fl_off[mid] <= t) p0 = mid + 1; else p1 = mid;
+              }
+              const int e = pool[fl_lo[p0 - 1] + (t - fl_off[p0 - 1])];
+              hits += sdr_bit(B, e) ? 1u : 0u;
+            }
+            kc_wave_lds_sync();
+          }
+          const uint64_t T2 = kc_wave_sum_u64(hits);
+          if (lane == 0) {
+            tot[d] += (unsigned long long)T2;
+            cur[d] = end;
+          }
+          kc_wave_lds_sync();
+          continue;
+        }
+        const int x = C[c];
+        if (lane == 0) cur[d] = c + 1;
+        kc_wave_lds_sync();
+        const int nx = lln[x];
+        if (nx <= l - 2 && !a.noprune) continue;
+        my_isect += (lane == 0);
+        my_work += lane == 0 ? (uint64_t)sz + (uint64_t)nx : 0u;
+        // C' = L_x with C: bitmap tests, hits compacted into level d+1
+        uint16_t* Cn = clist + (size_t)(d + 1) * SM;
+        uint32_t* Bn = bm + (size_t)(d + 1) * SMW;
+        for (int w = lane; w < SMW; w += 64) Bn[w] = 0u;
+        kc_wave_lds_sync();
+        const uint16_t* Lx = pool + lst[x];
+        int m = 0;
+        for (int i0 = 0; i0 < nx; i0 += 64) {
+          const int i = i0 + lane;
+          const int e = i < nx ? (int)Lx[i] : 0;
+          const bool hit = i < nx && sdr_bit(B, e);
+          const uint64_t mk = kc_ballot(hit);
+          if (hit) {
+            Cn[m + kc_mbcnt(mk)] = (uint16_t)e;
+            atomicOr(&Bn[e >> 5], 1u << (e & 31));
+          }
+          m += __popcll(mk);
+        }
+        kc_wave_lds_sync();
+        if (a.noprune ? m > 0 : m > l - 2) {
+          if (lane == 0) {
+            size[d + 1] = m;
+            cur[d + 1] = 0;
+            tot[d + 1] = 0;
+          }
+          kc_wave_lds_sync();
+          d++;
+          my_nodes += (lane == 0);
+        }
+      }
+      __syncthreads();
+      const unsigned long long T = tot[0];
+      if (lane == 0 && T) {
+        kc_add_checked(a.count, T, a.flags);
+        if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
+      }
+      {
+        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work),
+                       wn = kc_wave_sum_u64(my_nodes);
+        if (lane == 0) {
+          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+          if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
+          atomicAdd(&a.counters[0], (unsigned long long)wn);
+          atomicAdd(&a.counters[1], (unsigned long long)wi);
+          atomicAdd(&a.counters[2], (unsigned long long)ww);
+        }
+      }
+      my_nodes = my_isect = my_work = 0;
+      __syncthreads();
+    }
+  }
+}
+
 #define SD_LOGW_BINS 512
 #define SD_LOGW_SCALE 8.0f
 
@@ -456,6 +764,8 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   const int32_t R = c.nroots;
   if (R == 0) return KC_OK;
   const bool pv = c.pv != nullptr;
+  // the out-neighbour reduction counts (and logs) only
+  if (c.reduce && (pv || c.emit)) return KC_EUNSUPPORTED;
   const kc_options* opt = c.opt;
   int32_t *cls, *hist;
   float* logw;
@@ -593,6 +903,35 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     size_t bytes = 4 * words;
     a.e = c.emit ? *c.emit : kc_emit();
     a.noprune = c.opt && (c.opt->disable & KC_NO_PRUNE) ? 1 : 0;
+    a.pool = nullptr;
+    a.pool_cap = 0;
+    if (c.reduce) {
+      // G_u of up to 1088 vertices (the 1024-entry class): the reduced lists,
+      // at most SM (SM - 1) / 2 entries, in a per-workgroup pool
+      if (cl >= 3) return KC_EUNSUPPORTED;
+      const size_t rbytes = 4 * sdr_words(c.k, a.SMAX);
+      int dev = 0, maxlds = 65536;
+      KC_HIP(hipGetDevice(&dev));
+      KC_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      if (rbytes > (size_t)maxlds) return KC_EUNSUPPORTED;
+      auto rfn = k_sdegree_reduced;
+      KC_HIP(hipFuncSetAttribute((const void*)rfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rbytes));
+      int per_cu = 0;
+      KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rfn, 64, rbytes));
+      int64_t rgrid = (int64_t)(per_cu < 1 ? 1 : per_cu) * kc_device_cus();
+      if (rgrid > a.ntasks) rgrid = a.ntasks;
+      if (rgrid < 1) rgrid = 1;
+      a.gscratch = nullptr;
+      a.block_words = 0;
+      a.pool_cap = (int64_t)a.SMAX * (a.SMAX - 1) / 2 + 64;
+      KC_TRY(scr.get(&a.pool, (size_t)a.pool_cap * (size_t)rgrid));
+      if (c.size_only) continue;
+      hipLaunchKernelGGL(rfn, dim3((unsigned)rgrid), dim3(64), rbytes, st, a);
+      KC_HIP(hipGetLastError());
+      if (timed) KC_HIP(hipEventRecord(ev.ce[cl][1], st));
+      launches++;
+      continue;
+    }
     auto fn = pv ? k_sdegree_list<true, false> : (c.emit ? k_sdegree_list<false, true> : k_sdegree_list<false, false>);
     int64_t grid;
     size_t lds_bytes;

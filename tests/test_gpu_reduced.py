@@ -1,0 +1,112 @@
+"""SDegree with the out-neighbour reduction of Sec. 7.2 (orders
+'degree_reduced' and 'core_reduced'): Alg. 5 on each root's induced DAG G_u.
+
+Counts equal the definition; per-root joins, Lemma-2 work (|C| + |L_x| per
+join on G_u) and node counts equal the oracle's reduced recursion, for whole
+roots and for roots split into edge tasks, with and without pruning.  The
+outputs the reduced kernel does not produce (per-vertex, listing) and roots
+beyond its 1024-entry lists are refused, not approximated.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import _graphs as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2203_13512_amd as kc  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(g):
+    rp, ci = g
+    return (torch.from_numpy(np.ascontiguousarray(rp, dtype=np.int32)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ci, dtype=np.int32)).cuda())
+
+
+GRAPHS = [
+    ("er", lambda: graphgen.erdos_renyi(400, 0.06, planted=[14, 11, 9], seed=3)),
+    ("chunglu", lambda: graphgen.chung_lu(6000, 10.0, 2.1, 500.0, planted=[22, 16], seed=3)),
+    ("rmat", lambda: graphgen.rmat(11, 8, 0.57, 0.19, 0.19, 6, 12, 24, 0.9, seed=3)),
+    ("union", lambda: G.disjoint_union([G.complete(12), graphgen.erdos_renyi(90, 0.35, seed=3), G.complete(6)])),
+    ("bipartite", lambda: G.bipartite_with_clique(200, 150, 9)),
+]
+
+
+@pytest.mark.parametrize("order", ["degree_reduced", "core_reduced"])
+@pytest.mark.parametrize("name,make", GRAPHS, ids=[g[0] for g in GRAPHS])
+def test_reduced_sdegree_matches_oracle(order, name, make):
+    g = make()
+    rp, ci = dev(g)
+    for k in (3, 4, 5, 7):
+        want = oracle.count(*g, k)
+        for kw in (dict(), dict(split=1, split_threshold=1.0), dict(split=-1, chunk=3),
+                   dict(disable=kc.NO_PRUNE), dict(disable=kc.NO_PRUNE, split=1, split_threshold=1.0)):
+            say("reduced", name, order, k, kw)
+            total, pl, per = oracle.method_count(*g, k, order, disable=kw.get("disable", 0))
+            assert total == want
+            c, st = kc.count(rp, ci, k, order, root_logs=True, **kw)
+            assert c == want, kw
+            lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
+            assert st["prelist_count"] == pl
+            assert np.array_equal(lg["count"], per["count"].astype(np.int64)), kw
+            assert np.array_equal(lg["isect"], per["isect"].astype(np.int64)), kw
+            assert np.array_equal(lg["work"], per["work"].astype(np.int64)), kw
+            assert st["nodes"] == int(per["nodes"].sum()) and st["isect"] == int(per["isect"].sum())
+
+
+def test_reduction_lowers_the_logged_work():
+    """On the same graph and orientation the reduced recursion performs no
+    more joins and fewer Lemma-2 elements than the unreduced one."""
+    g = graphgen.chung_lu(20000, 12.0, 2.1, 800.0, planted=[30, 24], seed=5)
+    rp, ci = dev(g)
+    for k in (4, 6):
+        c0, s0 = kc.count(rp, ci, k, "degree", stats=True)
+        c1, s1 = kc.count(rp, ci, k, "degree_reduced", stats=True)
+        say("reduction", k, s0["isect"], s1["isect"], s0["work"], s1["work"], s0["list_ms"], s1["list_ms"])
+        assert c0 == c1 == oracle.count(*g, k)
+        assert s1["isect"] <= s0["isect"] and s1["work"] < s0["work"] and s1["nodes"] == s0["nodes"]
+
+
+def test_reduced_outputs_it_does_not_produce_are_refused():
+    g = dev(graphgen.erdos_renyi(300, 0.08, planted=[12], seed=2))
+    for order in ("degree_reduced", "core_reduced"):
+        with pytest.raises(kc.KCliqueError) as e:
+            kc.count(*g, 4, order, per_vertex=True)
+        assert e.value.status == kc.EUNSUPPORTED
+        with pytest.raises(kc.KCliqueError) as e:
+            kc.list_cliques(*g, 4, order, capacity=10)
+        assert e.value.status == kc.EUNSUPPORTED
+    # out-degrees above 1024 (the 4096-entry list class)
+    big = dev(G.complete_minus_edge(1030))
+    with pytest.raises(kc.KCliqueError) as e:
+        kc.count(*big, 4, "degree_reduced")
+    assert e.value.status == kc.EUNSUPPORTED
+
+
+def test_reduced_full_size_workload_2():
+    """Workload 2 (Chung-Lu, 1M vertices) at k = 5: the count equals the
+    oracle's golden count."""
+    import json
+    import os
+    with open(os.path.join(G.GOLDEN, "fullsize_w2_k5_degree.json")) as f:
+        gold = json.load(f)
+    w = G.workload_cached(2)
+    rp_h, ci_h = w.graphs[0]
+    assert G.graph_sha(rp_h, ci_h) == gold["graph_sha256"]
+    rp, ci = dev((rp_h, ci_h))
+    c, st = kc.count(rp, ci, 5, "degree_reduced", stats=True)
+    say("workload 2, k = 5, reduced SDegree:", c, "listing", round(st["list_ms"], 1), "ms; work", st["work"],
+        "joins", st["isect"])
+    assert c == gold["count"]
+    assert st["nodes"] == gold["nodes_total"]
+    assert st["work"] < gold["work_total"] and st["isect"] <= gold["isect_total"]
