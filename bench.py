@@ -109,8 +109,8 @@ def _cpu_worker(i_p):
 def _cpu_worker_sdegree(i_p):
     import oracle
     i, p, secs = i_p
-    drp, dci, k, roots = _CPU_JOB
-    return oracle.sdegree_count_roots(drp, dci, k, roots[i::p], seconds=secs)[:2]
+    drp, dci, k, roots, reduce = _CPU_JOB
+    return oracle.sdegree_count_roots(drp, dci, k, roots[i::p], seconds=secs, reduce=reduce)[:2]
 
 
 def cpu_baseline(rp_h, ci_h, k, order, secs):
@@ -131,14 +131,15 @@ def cpu_baseline(rp_h, ci_h, k, order, secs):
     t = time.perf_counter()
     removed = oracle.precore(rp_h, ci_h, k)
     removed, pl, _, _ = oracle.prelist(rp_h, ci_h, k, removed)
-    if order == "color":
+    if order in ("color", "core", "core_reduced"):
         drp, dci, _, _ = oracle.degeneracy_dag(rp_h, ci_h, removed)
     else:
         drp, dci = oracle.degree_dag(rp_h, ci_h, removed)[:2]
     prep_s = time.perf_counter() - t
     roots = np.flatnonzero(np.diff(drp) >= k - 1).astype(np.int32)
     roots = roots[np.random.default_rng(7).permutation(len(roots))]
-    _CPU_JOB = (drp, dci, k, roots)
+    reduce = order.endswith("_reduced")
+    _CPU_JOB = (drp, dci, k, roots) if order == "color" else (drp, dci, k, roots, reduce)
     worker = _cpu_worker if order == "color" else _cpu_worker_sdegree
     t = time.perf_counter()
     with mp.get_context("fork").Pool(procs) as pool:
@@ -146,7 +147,10 @@ def cpu_baseline(rp_h, ci_h, k, order, secs):
     el = time.perf_counter() - t
     c_cpu = sum(r[0] for r in res)
     done = sum(r[1] for r in res)
-    method = "BitCol on the degeneracy DAG" if order == "color" else "SDegree on the degree DAG"
+    method = {"color": "BitCol on the degeneracy DAG", "degree": "SDegree on the degree DAG",
+              "core": "SDegree on the degeneracy DAG",
+              "degree_reduced": "SDegree with the out-neighbour reduction on the degree DAG",
+              "core_reduced": "SDegree with the out-neighbour reduction on the degeneracy DAG"}[order]
     cpu = {"value": c_cpu / el, "unit": "k-cliques/s", "cores": procs, "kind": "oracle",
            "sample": f"the oracle's {method}, {procs} processes over disjoint strided slices of one fixed random "
                      f"order of the {len(roots)} roots, {secs:.0f}s each: {done} roots completed, {c_cpu} cliques "
@@ -217,9 +221,10 @@ def measured_peaks(torch):
 SD_CLASSES = [64, 256, 1024, 4096, 16384, 65536]
 
 
-def roofline_sdegree(st_list):
+def roofline_sdegree(st_list, order="degree"):
     """Roofline of SDegree's dominant listing launch: Lemma 2's cost |C| + d+_x
-    elements per merge join, 4 bytes each (the elements a join must read),
+    elements per merge join (with the out-neighbour reduction: |C| + |L_x| on
+    the root's induced DAG), 4 bytes each (the elements a join must read),
     against the HBM peak."""
     ncls = len(SD_CLASSES)
     cms = [statistics.fmean(st["class_ms"][c] for st in st_list) for c in range(ncls)]
@@ -230,7 +235,8 @@ def roofline_sdegree(st_list):
     list_ms = statistics.fmean(s["list_ms"] for s in st_list)
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 5), "traffic": None,
-            "kernel": f"k_sdegree_list, candidate lists of up to {SD_CLASSES[dom]} entries",
+            "kernel": f"{'k_sdegree_reduced' if order.endswith('_reduced') else 'k_sdegree_list'}, candidate "
+                      f"lists of up to {SD_CLASSES[dom]} entries",
             "launch_ms": round(cms[dom], 3), "launches_averaged": len(st_list),
             "lemma2_elements": int(st["class_work"][dom]), "tasks": int(st["class_tasks"][dom]),
             "all_classes": {str(SD_CLASSES[c]): {"ms": round(cms[c], 3), "elements": int(st["class_work"][c]),
@@ -411,7 +417,7 @@ def main():
                               "launch": {key: val for key, val in kwargs[v].items() if key != "mlp"}}
                           for v, r in done.items()},
             "roofline": with_measured_peak(roofline_of(R["stats"], w.name, k, head) if args.order == "color"
-                                           else roofline_sdegree(R["stats"]), peaks),
+                                           else roofline_sdegree(R["stats"], args.order), peaks),
             "cpu_baseline": cpu,
             # context only: the paper reports speedups of its methods over its
             # own CPU baselines (total serial time over its ten datasets), no rates

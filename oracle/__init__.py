@@ -71,7 +71,7 @@ def _load():
         "orc_bitcol_dag": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp],
         "orc_bitcol_roots": [i32, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp],
         "orc_bitcol_roots_timed": [i32, vp, vp, i32, i32, i32, vp, dbl, vp, vp],
-        "orc_sdegree_roots_timed": [i32, vp, vp, i32, i32, vp, dbl, vp, vp],
+        "orc_sdegree_roots_timed": [i32, vp, vp, i32, i32, i32, vp, dbl, vp, vp],
         "orc_sdegree_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_sdegree_reduced_roots": [i32, vp, vp, i32, i32, vp, vp, vp, vp, vp],
         "orc_merge_join": [vp, i32, vp, i32, vp],
@@ -313,15 +313,17 @@ def bitcol_count_roots(drp, dci, k: int, roots, seconds: float, L: int = 32):
     return int(c[0]), int(done[0]), st == OK
 
 
-def sdegree_count_roots(drp, dci, k: int, roots, seconds: float):
-    """SDegree from `roots` of the DAG in order until `seconds` pass (a timing
-    sample).  Returns (count, roots_completed, finished)."""
+def sdegree_count_roots(drp, dci, k: int, roots, seconds: float, reduce: bool = False):
+    """SDegree (with the out-neighbour reduction when `reduce`) from `roots`
+    of the DAG in order until `seconds` pass (a timing sample).  Returns
+    (count, roots_completed, finished)."""
     drp, dci = _csr(drp, dci)
     n = len(drp) - 1
     r = np.ascontiguousarray(roots, dtype=np.int32)
     c = np.zeros(1, dtype=np.uint64)
     done = np.zeros(1, dtype=np.int32)
-    st = _load().orc_sdegree_roots_timed(n, _p(drp), _p(dci), k, len(r), _p(r), float(seconds), _p(c), _p(done))
+    st = _load().orc_sdegree_roots_timed(n, _p(drp), _p(dci), k, 1 if reduce else 0, len(r), _p(r), float(seconds),
+                                         _p(c), _p(done))
     if st not in (OK, EBUDGET):
         _check(st, "sdegree_count_roots")
     return int(c[0]), int(done[0]), st == OK

@@ -916,9 +916,11 @@ static int bitcol_ws_init(bitcol_ws_t* w, int32_t n, const int32_t* drp, int32_t
 }
 
 /* SDegree from roots[0..nroots) in that order until `seconds` have passed (a
- * timing sample); outputs and status as orc_bitcol_roots_timed below. */
-int orc_sdegree_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t nroots,
-                            const int32_t* roots, double seconds, uint64_t* count, int32_t* roots_done) {
+ * timing sample), with the out-neighbour reduction when `reduce` is set;
+ * outputs and status as orc_bitcol_roots_timed below. */
+int orc_sdegree_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, int32_t k, int32_t reduce,
+                            int32_t nroots, const int32_t* roots, double seconds, uint64_t* count,
+                            int32_t* roots_done) {
   if (n < 0 || k < 3 || nroots < 0 || seconds <= 0.0) return ORC_EINVAL;
   for (int32_t i = 0; i < nroots; ++i)
     if (roots[i] < 0 || roots[i] >= n) return ORC_EINVAL;
@@ -938,7 +940,10 @@ int orc_sdegree_roots_timed(int32_t n, const int32_t* drp, const int32_t* dcol, 
   for (int32_t i = 0; i < nroots && !S.status; ++i) {
     int32_t u = roots[i];
     int32_t du = drp[u + 1] - drp[u];
-    if (du >= k - 1) {
+    if (reduce) {
+      const int st = sdegree_reduced_root(&S, drp, dcol, k, u);
+      if (st) { free(S.buf); return st; }
+    } else if (du >= k - 1) {
       memcpy(S.buf, dcol + drp[u], sizeof(int32_t) * (size_t)du);
       sdegree_list(&S, k - 1, S.buf, du, 0);
     }

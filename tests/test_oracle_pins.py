@@ -404,6 +404,8 @@ def test_timed_bitcol_sample_counts_what_the_roots_list():
     assert finished and done == len(droots) and c + pl == oracle.count(*g, k)
     c, done, finished = oracle.sdegree_count_roots(ddrp, ddci, k, droots, 1e-9)
     assert not finished and done == 1
+    c, done, finished = oracle.sdegree_count_roots(ddrp, ddci, k, droots, 600.0, reduce=True)
+    assert finished and c + pl == oracle.count(*g, k)
 
 
 def test_paper_bitcol_trace_on_the_encoded_example():
