@@ -371,10 +371,11 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
 // skipped when |L_x| <= l-2 and a join costs |C| + |L_x| (Lemma 2 on G_u).
 
 // LDS of a reduced-SDegree workgroup (32-bit words): ids[SM] | lst[SM] |
-// lln[SM] | clist[K][SM] u16 | bm[K][SM/32] | cur[K] | size[K] | tot[K] u64
-static size_t sdr_words(int k, int smax) {
+// lln[SM] | clist[K][SM] u16 | bm[K][SM/32] | cur[K] | size[K] | chosen[K] |
+// tot[K] u64 | cnt[SM] u64 (per-vertex output)
+static size_t sdr_words(int k, int smax, bool pv) {
   const size_t K = (size_t)k, S = (size_t)smax;
-  return 3 * S + K * S / 2 + K * (S / 32) + 4 * K + 8;
+  return 3 * S + K * S / 2 + K * (S / 32) + 5 * K + 8 + (pv ? 2 * S : 0);
 }
 
 // Stages the reduced lists of the candidates cand[0..nc) (positions of
@@ -458,6 +459,10 @@ __device__ void sdr_stage(const SdArgs& a, const int32_t* ids, int s, const uint
 
 __device__ __forceinline__ bool sdr_bit(const uint32_t* bm, int e) { return (bm[e >> 5] >> (e & 31)) & 1u; }
 
+// PV: per-vertex participation (each hit credits its own vertex and its
+// candidate, subtree totals flow to the vertices chosen above, as in
+// k_sdegree_list); EMIT: every clique written as k vertex ids.
+template <bool PV, bool EMIT>
 __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
   extern __shared__ uint32_t lds[];
   const int K = a.k;
@@ -470,7 +475,9 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
   uint32_t* bm = (uint32_t*)(clist + (size_t)K * SM);
   int32_t* cur = (int32_t*)(bm + (size_t)K * SMW);
   int32_t* size = cur + K;
-  unsigned long long* tot = (unsigned long long*)(((uintptr_t)(size + K) + 7) & ~(uintptr_t)7);
+  int32_t* chosen = size + K;  // positions of the vertices chosen above the current level
+  unsigned long long* tot = (unsigned long long*)(((uintptr_t)(chosen + K) + 7) & ~(uintptr_t)7);
+  unsigned long long* cnt = tot + K;
   uint16_t* pool = a.pool + (size_t)blockIdx.x * (size_t)a.pool_cap;
   const int lane = threadIdx.x;
   __shared__ int32_t sh_task[2];
@@ -501,6 +508,7 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
         lst[i] = -1;
         lln[i] = 0;
         clist[i] = (uint16_t)i;  // level 0: every position
+        if (PV) cnt[i] = 0;
       }
       for (int w = lane; w < SMW; w += 64) {
         const int lo = w * 32;
@@ -544,7 +552,10 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
         if (c >= end) {
           if (d == 0) break;
           const unsigned long long T = tot[d];
-          if (lane == 0) tot[d - 1] += T;
+          if (lane == 0) {
+            tot[d - 1] += T;
+            if (PV && T) atomicAdd(&cnt[chosen[d - 1]], T);
+          }
           kc_wave_lds_sync();
           d--;
           continue;
@@ -579,14 +590,41 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
             fl_off[lane] = incl - len;
             if (lane == 63) fl_off[64] = incl;
             kc_wave_lds_sync();
-            for (int t = lane; t < total_len; t += 64) {
-              int p0 = 0, p1 = 65;
-              while (p0 < p1) {
-                const int mid = (p0 + p1) >> 1;
-                if (fl_off[mid] <= t) p0 = mid + 1; else p1 = mid;
+            for (int t0 = 0; t0 < total_len; t0 += 64) {
+              const int t = t0 + lane;
+              bool hit = false;
+              int e = 0, seg = 0;
+              if (t < total_len) {
+                int p0 = 0, p1 = 65;
+                while (p0 < p1) {
+                  const int mid = (p0 + p1) >> 1;
+                  if (fl_off[mid] <= t) p0 = mid + 1; else p1 = mid;
+                }
+                seg = p0 - 1;
+                e = pool[fl_lo[seg] + (t - fl_off[seg])];
+                hit = sdr_bit(B, e);
               }
-              const int e = pool[fl_lo[p0 - 1] + (t - fl_off[p0 - 1])];
-              hits += sdr_bit(B, e) ? 1u : 0u;
+              hits += hit ? 1u : 0u;
+              if (PV && hit) {
+                atomicAdd(&cnt[e], 1ull);
+                atomicAdd(&cnt[C[b + seg]], 1ull);
+              }
+              if (EMIT) {
+                const uint64_t mk = kc_ballot(hit);
+                if (mk) {
+                  unsigned long long base = 0;
+                  if (lane == 0) base = atomicAdd(a.e.pos, (unsigned long long)__popcll(mk));
+                  base = (unsigned long long)__shfl((long long)base, 0, 64);
+                  const unsigned long long row = base + (unsigned long long)kc_mbcnt(mk);
+                  if (hit && row < (unsigned long long)a.e.cap) {
+                    int32_t* o = a.e.out + (int64_t)row * a.k;
+                    o[0] = u;
+                    for (int q = 0; q < d; ++q) o[1 + q] = ids[chosen[q]];
+                    o[1 + d] = ids[C[b + seg]];
+                    o[2 + d] = ids[e];
+                  }
+                }
+              }
             }
             kc_wave_lds_sync();
           }
@@ -626,6 +664,7 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
         kc_wave_lds_sync();
         if (a.noprune ? m > 0 : m > l - 2) {
           if (lane == 0) {
+            chosen[d] = x;
             size[d + 1] = m;
             cur[d + 1] = 0;
             tot[d + 1] = 0;
@@ -640,7 +679,13 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
       if (lane == 0 && T) {
         kc_add_checked(a.count, T, a.flags);
         if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
+        if (PV) kc_add_checked(&a.pv[u], T, a.flags);
       }
+      if (PV)
+        for (int i = lane; i < s0; i += 64) {
+          const unsigned long long cc = cnt[i];
+          if (cc) kc_add_checked(&a.pv[ids[i]], cc, a.flags);
+        }
       {
         const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work),
                        wn = kc_wave_sum_u64(my_nodes);
@@ -764,8 +809,6 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
   const int32_t R = c.nroots;
   if (R == 0) return KC_OK;
   const bool pv = c.pv != nullptr;
-  // the out-neighbour reduction counts (and logs) only
-  if (c.reduce && (pv || c.emit)) return KC_EUNSUPPORTED;
   const kc_options* opt = c.opt;
   int32_t *cls, *hist;
   float* logw;
@@ -909,12 +952,13 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
       // G_u of up to 1088 vertices (the 1024-entry class): the reduced lists,
       // at most SM (SM - 1) / 2 entries, in a per-workgroup pool
       if (cl >= 3) return KC_EUNSUPPORTED;
-      const size_t rbytes = 4 * sdr_words(c.k, a.SMAX);
+      const size_t rbytes = 4 * sdr_words(c.k, a.SMAX, pv);
       int dev = 0, maxlds = 65536;
       KC_HIP(hipGetDevice(&dev));
       KC_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
       if (rbytes > (size_t)maxlds) return KC_EUNSUPPORTED;
-      auto rfn = k_sdegree_reduced;
+      auto rfn = pv ? k_sdegree_reduced<true, false>
+                    : (c.emit ? k_sdegree_reduced<false, true> : k_sdegree_reduced<false, false>);
       KC_HIP(hipFuncSetAttribute((const void*)rfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rbytes));
       int per_cu = 0;
       KC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rfn, 64, rbytes));

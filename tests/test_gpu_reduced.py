@@ -3,9 +3,9 @@
 
 Counts equal the definition; per-root joins, Lemma-2 work (|C| + |L_x| per
 join on G_u) and node counts equal the oracle's reduced recursion, for whole
-roots and for roots split into edge tasks, with and without pruning.  The
-outputs the reduced kernel does not produce (per-vertex, listing) and roots
-beyond its 1024-entry lists are refused, not approximated.
+roots and for roots split into edge tasks, with and without pruning;
+per-vertex participation and the listing equal the oracle's.  Roots beyond
+its 1024-entry lists are refused, not approximated.
 """
 import sys
 
@@ -82,15 +82,28 @@ def test_reduction_lowers_the_logged_work():
         assert s1["isect"] <= s0["isect"] and s1["work"] < s0["work"] and s1["nodes"] == s0["nodes"]
 
 
-def test_reduced_outputs_it_does_not_produce_are_refused():
-    g = dev(graphgen.erdos_renyi(300, 0.08, planted=[12], seed=2))
-    for order in ("degree_reduced", "core_reduced"):
-        with pytest.raises(kc.KCliqueError) as e:
-            kc.count(*g, 4, order, per_vertex=True)
-        assert e.value.status == kc.EUNSUPPORTED
-        with pytest.raises(kc.KCliqueError) as e:
-            kc.list_cliques(*g, 4, order, capacity=10)
-        assert e.value.status == kc.EUNSUPPORTED
+@pytest.mark.parametrize("order", ["degree_reduced", "core_reduced"])
+def test_reduced_per_vertex_and_listing(order):
+    """Per-vertex participation equals the oracle's; the listing is the
+    oracle's set of k-cliques as sorted tuples (Sec. 3.1)."""
+    for name, make in GRAPHS:
+        g = make()
+        rp, ci = dev(g)
+        for k in (3, 4, 6):
+            say("reduced per-vertex / listing", name, order, k)
+            want, wpv = oracle.count(*g, k, per_vertex=True)
+            for kw in (dict(), dict(split=1, split_threshold=1.0)):
+                c, pv = kc.count(rp, ci, k, order, per_vertex=True, **kw)
+                assert c == want and np.array_equal(pv.cpu().numpy(), wpv.astype(np.int64)), kw
+            if want <= 200000:
+                rows, total = kc.list_cliques(rp, ci, k, order)
+                assert total == want
+                got = np.sort(rows.cpu().numpy(), axis=1)
+                exp, _ = oracle.list_cliques(*g, k)
+                assert np.array_equal(got[np.lexsort(got.T[::-1])], np.asarray(exp, dtype=np.int32))
+
+
+def test_reduced_roots_beyond_its_lists_are_refused():
     # out-degrees above 1024 (the 4096-entry list class)
     big = dev(G.complete_minus_edge(1030))
     with pytest.raises(kc.KCliqueError) as e:
