@@ -1143,8 +1143,13 @@ __global__ __launch_bounds__(64 * NW, GB ? 1 : 4) void k_bitcol_list(ListArgs a)
   uint64_t* rins = rows + 64;
   uint16_t* mlist = (uint16_t*)(rows + 204);
 
-  uint64_t my_nodes = 0, my_isect = 0;  // per lane
+  uint64_t my_nodes = 0, my_isect = 0;  // per lane, this task
   uint64_t my_wide = 0, my_comp = 0;    // of which: wave-wide joins, joins on re-encoded 64-bit rows
+  // this launch's totals (per lane; the count on thread 0), added to the
+  // device counters once at the end: per-task atomics on a handful of
+  // addresses serialise when the tasks are many and small
+  uint64_t run_nodes = 0, run_isect = 0, run_wide = 0, run_comp = 0, run_work = 0, run_count = 0;
+  bool run_ovf = false;
 
   for (;;) {
     if (tid == 0) {
@@ -1229,7 +1234,8 @@ __global__ __launch_bounds__(64 * NW, GB ? 1 : 4) void k_bitcol_list(ListArgs a)
       const uint64_t T = shtot[0];
       const int32_t u = a.roots[r];
       if (tid == 0 && T) {
-        kc_add_checked(a.count, T, a.flags);
+        run_ovf |= run_count + T < run_count;
+        run_count += T;
         if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
         if (PV) {
           kc_add_checked(&a.pv[u], T, a.flags);
@@ -1243,19 +1249,20 @@ __global__ __launch_bounds__(64 * NW, GB ? 1 : 4) void k_bitcol_list(ListArgs a)
           if (c) kc_add_checked(&a.pv[a.perm[po + p]], c, a.flags);
         }
       }
-      // per-root work log (flushed per task)
+      // work counters: the launch's totals, and the per-root log when asked
       {
-        const uint64_t wi = kc_wave_sum_u64(my_isect), wn = kc_wave_sum_u64(my_nodes);
-        const uint64_t ww = kc_wave_sum_u64(my_wide), wc = kc_wave_sum_u64(my_comp);
-        if (lane == 0 && (wi || wn)) {
-          atomicAdd(&a.counters[3], (unsigned long long)ww);
-          atomicAdd(&a.counters[4], (unsigned long long)wc);
-          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
-          if (a.root_work)
-            atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)wi * (uint64_t)((s + 31) / 32));
-          atomicAdd(&a.counters[0], (unsigned long long)wn);
-          atomicAdd(&a.counters[1], (unsigned long long)wi);
-          atomicAdd(&a.counters[2], (unsigned long long)wi * (uint64_t)((s + 31) / 32));
+        const uint64_t ws = (uint64_t)((s + 31) / 32);
+        run_nodes += my_nodes;
+        run_isect += my_isect;
+        run_wide += my_wide;
+        run_comp += my_comp;
+        run_work += my_isect * ws;
+        if (a.root_isect || a.root_work) {
+          const uint64_t wi = kc_wave_sum_u64(my_isect);
+          if (lane == 0 && wi) {
+            if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+            if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)(wi * ws));
+          }
         }
       }
       my_nodes = 0;
@@ -1263,6 +1270,21 @@ __global__ __launch_bounds__(64 * NW, GB ? 1 : 4) void k_bitcol_list(ListArgs a)
       my_wide = 0;
       my_comp = 0;
       __syncthreads();
+    }
+  }
+  {
+    const uint64_t wn = kc_wave_sum_u64(run_nodes), wi = kc_wave_sum_u64(run_isect);
+    const uint64_t ww = kc_wave_sum_u64(run_wide), wc = kc_wave_sum_u64(run_comp), wk = kc_wave_sum_u64(run_work);
+    if (lane == 0 && (wi || wn)) {
+      atomicAdd(&a.counters[0], (unsigned long long)wn);
+      atomicAdd(&a.counters[1], (unsigned long long)wi);
+      atomicAdd(&a.counters[2], (unsigned long long)wk);
+      atomicAdd(&a.counters[3], (unsigned long long)ww);
+      atomicAdd(&a.counters[4], (unsigned long long)wc);
+    }
+    if (tid == 0) {
+      kc_add_checked(a.count, run_count, a.flags);
+      if (run_ovf) atomicOr(a.flags, KC_FLAG_OVERFLOW);
     }
   }
 }

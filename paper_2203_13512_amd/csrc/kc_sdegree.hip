@@ -87,6 +87,20 @@ __device__ __forceinline__ int sd_lower_bound(const int32_t* a, int lo, int hi, 
   return lo;
 }
 
+// Adds a launch's work totals (per lane) and clique count (lane 0) to the
+// device counters, once per wave.
+__device__ __forceinline__ void sd_flush_counters(const SdArgs& a, int lane, uint64_t nodes, uint64_t isect,
+                                                  uint64_t work, uint64_t count, bool ovf) {
+  const uint64_t wn = kc_wave_sum_u64(nodes), wi = kc_wave_sum_u64(isect), ww = kc_wave_sum_u64(work);
+  if (lane == 0) {
+    if (wn) atomicAdd(&a.counters[0], (unsigned long long)wn);
+    if (wi) atomicAdd(&a.counters[1], (unsigned long long)wi);
+    if (ww) atomicAdd(&a.counters[2], (unsigned long long)ww);
+    kc_add_checked(a.count, count, a.flags);
+    if (ovf) atomicOr(a.flags, KC_FLAG_OVERFLOW);
+  }
+}
+
 // EMIT: write every clique found (the emit step of Alg. 5: R + {x, y} for
 // each hit y of a join at l = 2), rows reserved per 64-entry chunk with one
 // atomic; `chosen` then holds the vertex ids of R.
@@ -107,7 +121,11 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
   __shared__ int32_t sh_task[2];
   __shared__ int32_t fl_lo[64], fl_off[65];  // flattened level-2 joins: range starts and offsets
 
-  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;  // per lane; summed over the wave per task
+  uint64_t my_nodes = 0, my_isect = 0, my_work = 0;  // per lane, this task
+  // the launch's totals (per lane; the count on lane 0), added to the device
+  // counters once at the end rather than per task
+  uint64_t run_nodes = 0, run_isect = 0, run_work = 0, run_count = 0;
+  bool run_ovf = false;
   for (;;) {
     if (lane == 0) {
       unsigned long long t = atomicAdd(a.head, (unsigned long long)a.chunk);
@@ -326,7 +344,8 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
       __syncthreads();
       const unsigned long long T = tot[0];
       if (lane == 0 && T) {
-        kc_add_checked(a.count, T, a.flags);
+        run_ovf |= run_count + T < run_count;
+        run_count += T;
         if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
         if (PV) kc_add_checked(&a.pv[u], T, a.flags);
       }
@@ -335,21 +354,21 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
           unsigned long long cc = cnt[i];
           if (cc) kc_add_checked(&a.pv[a.dcol[b0 + i]], cc, a.flags);
         }
-      {
-        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work),
-                       wn = kc_wave_sum_u64(my_nodes);
+      run_nodes += my_nodes;
+      run_isect += my_isect;
+      run_work += my_work;
+      if (a.root_isect || a.root_work) {
+        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work);
         if (lane == 0) {
-          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
-          if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
-          atomicAdd(&a.counters[0], (unsigned long long)wn);
-          atomicAdd(&a.counters[1], (unsigned long long)wi);
-          atomicAdd(&a.counters[2], (unsigned long long)ww);
+          if (a.root_isect && wi) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+          if (a.root_work && ww) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
         }
       }
       my_nodes = my_isect = my_work = 0;
       __syncthreads();
     }
   }
+  sd_flush_counters(a, lane, run_nodes, run_isect, run_work, run_count, run_ovf);
 }
 
 
@@ -484,6 +503,8 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
   __shared__ int32_t fl_lo[64], fl_off[65], fl_cnt[64];
 
   uint64_t my_nodes = 0, my_isect = 0, my_work = 0;
+  uint64_t run_nodes = 0, run_isect = 0, run_work = 0, run_count = 0;  // the launch's totals
+  bool run_ovf = false;
   for (;;) {
     if (lane == 0) {
       unsigned long long t = atomicAdd(a.head, (unsigned long long)a.chunk);
@@ -677,7 +698,8 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
       __syncthreads();
       const unsigned long long T = tot[0];
       if (lane == 0 && T) {
-        kc_add_checked(a.count, T, a.flags);
+        run_ovf |= run_count + T < run_count;
+        run_count += T;
         if (a.root_count) kc_add_checked(&a.root_count[u], T, a.flags);
         if (PV) kc_add_checked(&a.pv[u], T, a.flags);
       }
@@ -686,21 +708,21 @@ __global__ __launch_bounds__(64) void k_sdegree_reduced(SdArgs a) {
           const unsigned long long cc = cnt[i];
           if (cc) kc_add_checked(&a.pv[ids[i]], cc, a.flags);
         }
-      {
-        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work),
-                       wn = kc_wave_sum_u64(my_nodes);
+      run_nodes += my_nodes;
+      run_isect += my_isect;
+      run_work += my_work;
+      if (a.root_isect || a.root_work) {
+        const uint64_t wi = kc_wave_sum_u64(my_isect), ww = kc_wave_sum_u64(my_work);
         if (lane == 0) {
-          if (a.root_isect) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
-          if (a.root_work) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
-          atomicAdd(&a.counters[0], (unsigned long long)wn);
-          atomicAdd(&a.counters[1], (unsigned long long)wi);
-          atomicAdd(&a.counters[2], (unsigned long long)ww);
+          if (a.root_isect && wi) atomicAdd((unsigned long long*)&a.root_isect[u], (unsigned long long)wi);
+          if (a.root_work && ww) atomicAdd((unsigned long long*)&a.root_work[u], (unsigned long long)ww);
         }
       }
       my_nodes = my_isect = my_work = 0;
       __syncthreads();
     }
   }
+  sd_flush_counters(a, lane, run_nodes, run_isect, run_work, run_count, run_ovf);
 }
 
 #define SD_LOGW_BINS 512
