@@ -124,6 +124,7 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
   uint32_t* M2 = M1 + (size_t)WM * S;
   const int lane = threadIdx.x;
 
+  uint64_t staged_bytes = 0;  // lane 0: algorithmic bytes of the roots this workgroup staged
   for (int32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
     const int32_t r = list[li];
     const int32_t u = a.roots[r];
@@ -286,10 +287,12 @@ __global__ __launch_bounds__(64) void k_bitcol_stage(StageArgs a, const int32_t*
         a.features[4 * (int64_t)r + 2] = (float)maxc;
         a.features[4 * (int64_t)r + 3] = (float)edges;
       }
-      atomicAdd(a.stage_bytes, (unsigned long long)(4ull * ((uint64_t)s + (uint64_t)T)));
+      staged_bytes += 4ull * ((uint64_t)s + (uint64_t)T);
     }
     stage_sync(mat);
   }
+  // one atomic per workgroup for the staging counter, not one per root
+  if (lane == 0 && staged_bytes) atomicAdd(a.stage_bytes, (unsigned long long)staged_bytes);
 }
 
 // ============================================================== listing
