@@ -7,9 +7,11 @@ cliques listed from each root, the same joins and the same work (compared as
 SHA-256 digests of the per-vertex arrays).  BitCol runs in the benchmark's
 launch configuration (learned schedule, tuned launch shape) and under the
 degree schedule; these workloads put roots into the 8-, 12- and 16-word
-bitmap classes, which carry most of the benchmark's listing time.  The
-batched workload (256 graphs with their own k) is checked graph by graph,
-eagerly and through every replay of a prepared plan.
+bitmap classes, which carry most of the benchmark's listing time.  Workloads
+beyond the oracle's full enumeration are checked on sampled roots of every
+wide word class (tests/golden/make_sampled.py).  The batched workload (256
+graphs with their own k) is checked graph by graph, eagerly and through
+every replay of a prepared plan.
 """
 import glob
 import json
@@ -79,6 +81,36 @@ def test_fullsize_per_root_parity(path):
         assert st["nodes"] == gd["nodes_total"]
         if order == "color":
             assert st["max_core"] == gd["max_core"]
+
+
+SAMPLED = sorted(glob.glob(os.path.join(G.GOLDEN, "sampled_w[0-9]_k*_color.json")))
+
+
+@pytest.mark.parametrize("path", SAMPLED, ids=[os.path.basename(p)[:-5] for p in SAMPLED])
+def test_sampled_root_parity(path):
+    """Workloads whose full enumeration is beyond the oracle: the cliques,
+    BitJoins and words of the cheapest roots of the 8-, 12-, 16- and
+    24-word classes (tests/golden/make_sampled.py), from the whole GPU run."""
+    gd = _load(path)
+    w = G.workload_cached(gd["cfg"])
+    rp_h, ci_h = w.graphs[0]
+    assert G.graph_sha(rp_h, ci_h) == gd["graph_sha256"], "the generator no longer makes the stored graph"
+    k = gd["k"]
+    rp = torch.from_numpy(rp_h).cuda()
+    ci = torch.from_numpy(ci_h).cuda()
+    roots = np.asarray(gd["roots"], dtype=np.int64)
+    tuned = autotune.lookup(rp_h, ci_h, k, "color", schedule="learned")
+    for kw in (dict(schedule="learned", mlp=scheduler.load_model(rp.device, k), **tuned), dict(schedule="degree")):
+        say(os.path.basename(path), {key: v for key, v in kw.items() if key != "mlp"})
+        c, st = kc.count(rp, ci, k, "color", root_logs=True, **kw)
+        lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
+        assert st["prelist_count"] == gd["prelist_count"]
+        assert np.array_equal(lg["features"][roots, 0].astype(np.int64), gd["out_degree"])
+        assert np.array_equal(lg["features"][roots, 1].astype(np.int64), gd["core"])
+        assert np.array_equal(lg["count"][roots], np.asarray(gd["count"], dtype=np.int64))
+        assert np.array_equal(lg["isect"][roots], np.asarray(gd["isect"], dtype=np.int64))
+        assert np.array_equal(lg["work"][roots], np.asarray(gd["words"], dtype=np.int64))
+        assert int(lg["count"].sum()) == c
 
 
 @pytest.mark.skipif(not os.path.exists(BATCH), reason="no stored batch counts")
