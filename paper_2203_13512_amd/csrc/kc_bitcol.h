@@ -347,10 +347,8 @@ struct ListLayout {
   static constexpr int oC0 = oFirst + KC_KMAX + 2;
   static constexpr int oSh = a2(oC0 + W);
   static constexpr int oWave = a4(oSh + 16);
-  // Two-word re-encoding (sets of 65..128 members) is used when counting, in
-  // the LDS classes of up to 24 words (for 32 words its region would halve
-  // the waves per workgroup).
-  static constexpr bool C2 = COMP && !PV && W >= 4 && W <= 24;
+  // Two-word re-encoding (sets of 65..128 members) is used when counting.
+  static constexpr bool C2 = COMP && !PV && W >= 4 && W <= 16;
   // Per-wave region used by one evaluation at a time: the candidate list of a
   // lane-parallel level-3 node, or a re-encoded node (rows, queue or in-rows,
   // color masks, member list).
@@ -999,7 +997,7 @@ __device__ uint64_t eval_node(const uint32_t* __restrict__ Bl, const uint32_t* _
                               uint16_t* __restrict__ vlist, uint64_t& joins, uint64_t& nodes, uint64_t& wjoins,
                               uint64_t& cjoins, unsigned long long* cnt, int part, int nparts, int cmax, int clev,
                               int32_t* __restrict__ shared_next, uint32_t* __restrict__ ureg) {
-  constexpr bool C2 = COMP && !PV && W >= 4 && W <= 24;
+  constexpr bool C2 = COMP && !PV && W >= 4 && W <= 16;
   const uint32_t m = split_popc(cw);
   if (COMP && (int)m <= cmax && (int)m <= 64 && L <= KC_CMAX && L >= clev) {
     const uint64_t j0 = joins;
