@@ -150,7 +150,16 @@ typedef struct {
   const int32_t* vertex_k;/* device pointer, n entries, or NULL: a k per vertex (constant on every
                              connected component; the k argument must be their maximum).  Used to count
                              many graphs with different k in one call. */
-  void* workspace;         /* device memory owned by the caller, or NULL: the call takes all its scratch
+  const uint8_t* root_mask;/* device pointer, n entries, or NULL (= every vertex): a share of the roots.
+                             Only vertices u with root_mask[u] != 0 are listed from as roots (Theorem 1
+                             gives each k-clique exactly one root, its first vertex in the orientation),
+                             and the Pre-List cliques of a clique component (Alg. 4) are reported when
+                             the mask is set at the component's smallest vertex.  Preprocessing and the
+                             orientation still see the whole graph, so over masks that partition the
+                             vertices the counts, per-vertex values and listed rows add up to those of
+                             the unmasked call.  Requires device_ptrs and k >= 3 (else KC_EINVAL,
+                             KC_EUNSUPPORTED); not for batched calls and plans (KC_EINVAL). */
+  void* workspace;        /* device memory owned by the caller, or NULL: the call takes all its scratch
                              memory from it (no device allocation by the library); its contents on
                              entry are irrelevant and on return unspecified.  At least the size
                              kclique_workspace_size reports for the same arguments and options. */

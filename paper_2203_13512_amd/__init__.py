@@ -65,7 +65,7 @@ class Options(ctypes.Structure):
         ("class_streams", ctypes.c_int32), ("disable", ctypes.c_int32), ("split_policy", ctypes.c_int32),
         ("root_work", ctypes.c_void_p), ("root_isect", ctypes.c_void_p),
         ("root_features", ctypes.c_void_p), ("root_count", ctypes.c_void_p), ("vertex_k", ctypes.c_void_p),
-        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+        ("root_mask", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stats", ctypes.POINTER(Stats)),
     ]
 
@@ -166,6 +166,20 @@ def _options(schedule="degree", mlp=None, trusted=False, **launch):
     return opt, keep
 
 
+def _root_mask(opt, root_mask, n, keep):
+    """Sets kc_options.root_mask from a CUDA bool or uint8 tensor of n entries."""
+    if root_mask is None:
+        return
+    import torch
+    if not (_is_torch(root_mask) and root_mask.is_cuda):
+        raise ValueError("root_mask must be a CUDA tensor (with the graph on the GPU)")
+    if root_mask.dtype not in (torch.bool, torch.uint8) or root_mask.numel() != n:
+        raise ValueError("root_mask must hold n bool or uint8 entries")
+    m = root_mask.contiguous().view(torch.uint8)
+    opt.root_mask = m.data_ptr()
+    keep.append(m)
+
+
 def _device_csr(row_ptr, col_idx):
     import torch
     rp = row_ptr.contiguous()
@@ -176,7 +190,7 @@ def _device_csr(row_ptr, col_idx):
 
 
 def workspace_size(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False,
-                   schedule: str = "degree", mlp=None, trusted: bool = False, **launch) -> int:
+                   schedule: str = "degree", mlp=None, trusted: bool = False, root_mask=None, **launch) -> int:
     """Bytes of device scratch a count() with the same arguments takes from a
     caller-owned workspace (``kclique_workspace_size``: runs the call's
     preparation on the device and stops before the listing)."""
@@ -186,10 +200,13 @@ def workspace_size(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex
         rp, ci = _device_csr(row_ptr, col_idx)
         opt.device_ptrs = 1
         opt.stream = _torch_stream(rp.device)
+        _root_mask(opt, root_mask, rp.numel() - 1, keep)
         rc = _lib().kclique_workspace_size(rp.numel() - 1, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k,
                                            ORDERS[order], 1 if per_vertex else 0, ctypes.byref(opt),
                                            ctypes.byref(out))
     else:
+        if root_mask is not None:
+            raise ValueError("root_mask takes a graph on the GPU")
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         rc = _lib().kclique_workspace_size(len(rp) - 1, rp.ctypes.data, ci.ctypes.data if ci.size else None, k,
@@ -201,7 +218,7 @@ def workspace_size(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex
 
 def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = False, schedule: str = "degree",
           mlp=None, trusted: bool = False, root_logs: bool = False, stats: bool = False, workspace=None,
-          **launch):
+          root_mask=None, **launch):
     """Number of k-cliques (and per-vertex participation).
 
     Returns ``count`` or, with ``per_vertex``, ``(count, pv)`` where pv[v]
@@ -212,7 +229,10 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
     attributed to the vertex) are added to that dict.  ``workspace``: None
     (the library allocates its scratch), a CUDA uint8 tensor owned by the
     caller (at least workspace_size() bytes), or "torch" (sized with
-    workspace_size() and allocated by torch for this call).  ``launch``:
+    workspace_size() and allocated by torch for this call).  ``root_mask``
+    (GPU input, k >= 3): a CUDA bool/uint8 tensor of n entries; only the
+    share of the roots it marks is listed (kc_options.root_mask: results over
+    masks that partition the vertices add up to the unmasked call's).  ``launch``:
     waves_per_root, chunk, split, split_threshold, compress, compress_level,
     class_streams, split_policy, disable (kc_options; none changes a result).
     """
@@ -227,7 +247,7 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
             raise ValueError("workspace must be None, a device tensor or 'torch'")
         import torch
         nbytes = workspace_size(row_ptr, col_idx, k, order, per_vertex=per_vertex, schedule=schedule, mlp=mlp,
-                                trusted=trusted, **launch)
+                                trusted=trusted, root_mask=root_mask, **launch)
         dev = row_ptr.device if on_gpu else torch.device("cuda")
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     if workspace is not None:
@@ -241,6 +261,7 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
         dev = rp.device
         opt.device_ptrs = 1
         opt.stream = _torch_stream(dev)
+        _root_mask(opt, root_mask, n, keep)
         pv = torch.zeros(max(n, 1), dtype=torch.int64, device=dev) if per_vertex else None
         logs = None
         if root_logs:
@@ -264,8 +285,8 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
                 d["root_logs"] = {key: v[:n] for key, v in logs.items()}
             res.append(d)
     else:
-        if root_logs or schedule == "learned":
-            raise ValueError("root logs and the learned schedule take GPU tensors")
+        if root_logs or schedule == "learned" or root_mask is not None:
+            raise ValueError("root logs, root masks and the learned schedule take GPU tensors")
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         n = len(rp) - 1
@@ -282,15 +303,15 @@ def count(row_ptr, col_idx, k: int, order: str = "color", *, per_vertex: bool = 
 
 
 def list_cliques(row_ptr, col_idx, k: int, order: str = "color", capacity: int | None = None, *,
-                 trusted: bool = False, workspace=None, **launch):
+                 trusted: bool = False, workspace=None, root_mask=None, **launch):
     """Every k-clique (``kclique_list``): returns (rows, total), rows an
     int32 array of shape (min(total, capacity), k) of vertex ids (a torch
     tensor on the GPU for GPU input, numpy otherwise; row order and the order
     inside a row are unspecified).  Without ``capacity`` the total is counted
-    first and the buffer sized to it."""
+    first and the buffer sized to it.  ``root_mask`` as for count()."""
     L = _lib()
     if capacity is None:
-        capacity = count(row_ptr, col_idx, k, order, trusted=trusted)
+        capacity = count(row_ptr, col_idx, k, order, trusted=trusted, root_mask=root_mask)
     opt, keep = _options("degree", None, trusted, **launch)
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
@@ -302,10 +323,13 @@ def list_cliques(row_ptr, col_idx, k: int, order: str = "color", capacity: int |
         rp, ci = _device_csr(row_ptr, col_idx)
         opt.device_ptrs = 1
         opt.stream = _torch_stream(rp.device)
+        _root_mask(opt, root_mask, rp.numel() - 1, keep)
         out = torch.empty((max(capacity, 1), k), dtype=torch.int32, device=rp.device)
         rc = L.kclique_list(rp.numel() - 1, rp.data_ptr(), ci.data_ptr() if ci.numel() else None, k, ORDERS[order],
                             ctypes.byref(opt), out.data_ptr(), capacity, ctypes.byref(written), ctypes.byref(total))
     else:
+        if root_mask is not None:
+            raise ValueError("root_mask takes a graph on the GPU")
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         out = np.empty((max(capacity, 1), k), dtype=np.int32)

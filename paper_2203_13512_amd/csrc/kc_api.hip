@@ -32,11 +32,11 @@ extern "C" const char* kc_status_string(int status) {
   return "unknown status";
 }
 
-__global__ void k_roots(int32_t n, const int32_t* __restrict__ drp, int32_t km1, const int32_t* vk, int32_t* roots,
-                        int32_t* nroots, int32_t* max_dplus) {
+__global__ void k_roots(int32_t n, const int32_t* __restrict__ drp, int32_t km1, const int32_t* vk,
+                        const uint8_t* __restrict__ mask, int32_t* roots, int32_t* nroots, int32_t* max_dplus) {
   int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
   int32_t d = u < n ? drp[u + 1] - drp[u] : 0;
-  bool take = u < n && d >= kc_vk(vk, u, km1 + 1) - 1;
+  bool take = u < n && d >= kc_vk(vk, u, km1 + 1) - 1 && (!mask || mask[u]);
   uint64_t m = kc_ballot(take);
   int base = 0;
   if (kc_lane() == 0 && m) base = atomicAdd(nroots, __popcll(m));
@@ -224,6 +224,9 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   const int32_t* vk = opt->vertex_k;
   if (vk && !opt->device_ptrs) return KC_EINVAL;
   if (vk && k < 3) return KC_EUNSUPPORTED;
+  const uint8_t* mask = opt->root_mask;
+  if (mask && !opt->device_ptrs) return KC_EINVAL;
+  if (mask && k < 3) return KC_EUNSUPPORTED;
   if (k <= 2 || (k > n && !vk)) {
     if (cap) return KC_EUNSUPPORTED;
     // linear cases and the empty answer
@@ -257,13 +260,13 @@ static int count_impl(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
     if (k > KC_KMAX_LIMIT) return KC_EUNSUPPORTED;
     kc_prep_out prep;
     KC_TRY(kc_preprocess(g, k, vk, order, prelist_d, pv_d, (unsigned long long*)opt->root_count, flags, &prep,
-                         scr, s, listing ? &em : nullptr, opt->disable));
+                         scr, s, listing ? &em : nullptr, opt->disable, mask));
     KC_TRY(ev.record(1, s));
     int32_t *roots, *rinfo;
     KC_TRY(scr.get(&roots, (size_t)n + 1));
     KC_TRY(scr.get(&rinfo, 4));
     KC_HIP(hipMemsetAsync(rinfo, 0, sizeof(int32_t) * 4, s));
-    k_roots<<<(n + 255) / 256, 256, 0, s>>>(n, prep.drp, k - 1, vk, roots, rinfo, rinfo + 1);
+    k_roots<<<(n + 255) / 256, 256, 0, s>>>(n, prep.drp, k - 1, vk, mask, roots, rinfo, rinfo + 1);
     KC_HIP(hipGetLastError());
     int32_t hr[2] = {0, 0};
     KC_HIP(hipMemcpyAsync(hr, rinfo, sizeof(hr), hipMemcpyDeviceToHost, s));
@@ -591,6 +594,7 @@ static kc_options union_options(const kc_options& o, const BatchUnion& U, unsign
   u.workspace = nullptr;  // batched calls and plans allocate their own scratch
   u.workspace_bytes = 0;
   u.vertex_k = U.vk;
+  u.root_mask = nullptr;
   u.root_count = (uint64_t*)rc;
   u.root_work = nullptr;
   u.root_isect = nullptr;
@@ -624,6 +628,7 @@ extern "C" int kclique_count_batched(int32_t num_graphs, const int32_t* n, const
   kc_options o;
   if (opt) o = *opt;
   else memset(&o, 0, sizeof(o));
+  if (o.root_mask) return KC_EINVAL;  // a mask over the union's vertices is not offered
   hipStream_t s = (hipStream_t)o.stream;
   const bool dev_in = o.device_ptrs != 0;
   kc_scratch scr(s);
@@ -691,6 +696,7 @@ static int plan_batched(int32_t num_graphs, const int32_t* n, const int64_t* row
   kc_options o;
   if (opt) o = *opt;
   else memset(&o, 0, sizeof(o));
+  if (o.root_mask) return KC_EINVAL;
   const bool dev_in = o.device_ptrs != 0;
   P->dev_out = dev_in;
   KC_HIP(hipGetDevice(&P->device));

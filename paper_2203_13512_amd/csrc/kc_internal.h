@@ -172,7 +172,7 @@ int kc_validate_graph(const kc_dev_graph& g, int* flags_dev, hipStream_t s);
 int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
                   unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
                   int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s, const kc_emit* emit = nullptr,
-                  int32_t disable = 0);
+                  int32_t disable = 0, const uint8_t* root_mask = nullptr);
 
 // Listing (kc_sdegree.hip, kc_bitcol.hip).
 struct kc_list_ctx {

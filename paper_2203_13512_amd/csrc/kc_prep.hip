@@ -269,7 +269,7 @@ __global__ void k_uf_stats(int32_t n, const uint8_t* removed, int32_t* parent, c
 __global__ void k_prelist_roots(int32_t n, int32_t k, const int32_t* vk, const uint8_t* removed,
                                 const int32_t* parent, const int32_t* comp_n, const unsigned long long* comp_dsum,
                                 uint8_t* is_clique, unsigned long long* prelist_count,
-                                unsigned long long* root_count, int* flags) {
+                                unsigned long long* root_count, int* flags, const uint8_t* mask) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   is_clique[v] = 0;
@@ -277,6 +277,7 @@ __global__ void k_prelist_roots(int32_t n, int32_t k, const int32_t* vk, const u
   uint64_t nc = (uint64_t)comp_n[v];
   if (comp_dsum[v] != nc * (nc - 1)) return;
   is_clique[v] = 1;
+  if (mask && !mask[v]) return;  // reported by the share that holds the smallest vertex
   uint64_t c;
   if (!kc_binom(nc, (uint64_t)kc_vk(vk, v, k), &c)) { atomicOr(flags, KC_FLAG_OVERFLOW); return; }
   kc_add_checked(prelist_count, c, flags);
@@ -285,13 +286,13 @@ __global__ void k_prelist_roots(int32_t n, int32_t k, const int32_t* vk, const u
 
 __global__ void k_prelist_remove(int32_t n, int32_t k, const int32_t* vk, uint8_t* removed,
                                  const int32_t* parent, const int32_t* comp_n, const uint8_t* is_clique,
-                                 unsigned long long* pv, int* flags) {
+                                 unsigned long long* pv, int* flags, const uint8_t* mask) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || removed[v]) return;
   int32_t r = parent[v];
   if (!is_clique[r]) return;
   removed[v] = 1;
-  if (pv) {
+  if (pv && (!mask || mask[r])) {
     uint64_t c;
     if (!kc_binom((uint64_t)comp_n[r] - 1, (uint64_t)kc_vk(vk, v, k) - 1, &c)) {
       atomicOr(flags, KC_FLAG_OVERFLOW);
@@ -311,10 +312,11 @@ __global__ void k_prelist_remove(int32_t n, int32_t k, const int32_t* vk, uint8_
 // t - C(a_k, k), and so on.
 __global__ void k_pl_sizes(int32_t n, int32_t k, const int32_t* vk, const uint8_t* __restrict__ removed,
                            const int32_t* __restrict__ parent, const uint8_t* __restrict__ is_clique,
-                           const int32_t* __restrict__ comp_n, int64_t cap, int32_t* msz, int64_t* tsz) {
+                           const int32_t* __restrict__ comp_n, int64_t cap, const uint8_t* mask, int32_t* msz,
+                           int64_t* tsz) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const bool root = !removed[v] && parent[v] == v && is_clique[v];
+  const bool root = !removed[v] && parent[v] == v && is_clique[v] && (!mask || mask[v]);
   uint64_t c = 0;
   if (root && !kc_binom((uint64_t)comp_n[v], (uint64_t)kc_vk(vk, v, k), &c)) c = ~0ull;
   msz[v] = root ? comp_n[v] : 0;
@@ -322,12 +324,12 @@ __global__ void k_pl_sizes(int32_t n, int32_t k, const int32_t* vk, const uint8_
 }
 
 __global__ void k_pl_members(int32_t n, const uint8_t* __restrict__ removed, const int32_t* __restrict__ parent,
-                             const uint8_t* __restrict__ is_clique, const int32_t* __restrict__ moff, int32_t* fill,
-                             int32_t* members) {
+                             const uint8_t* __restrict__ is_clique, const uint8_t* mask,
+                             const int32_t* __restrict__ moff, int32_t* fill, int32_t* members) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || removed[v]) return;
   const int32_t r = parent[v];
-  if (!is_clique[r]) return;
+  if (!is_clique[r] || (mask && !mask[r])) return;
   members[moff[r] + atomicAdd(&fill[r], 1)] = v;
 }
 
@@ -512,7 +514,7 @@ static int read_i32(const int32_t* dev, int32_t* host, hipStream_t s) {
 int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t order,
                   unsigned long long* prelist_count_dev, unsigned long long* pv_dev, unsigned long long* root_count,
                   int* flags_dev, kc_prep_out* out, kc_scratch& scr, hipStream_t s, const kc_emit* emit,
-                  int32_t disable) {
+                  int32_t disable, const uint8_t* mask) {
   const int32_t n = g.n;
   const int32_t km1 = k - 1;
   memset(out, 0, sizeof(*out));
@@ -561,7 +563,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
       k_uf_hook<<<grid_for((int64_t)n * KC_WAVE), 256, 0, s>>>(n, g.rp, g.col, out->removed, parent);
       k_uf_stats<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, out->deg, comp_n, comp_dsum);
       k_prelist_roots<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, comp_dsum, is_clique,
-                                                   prelist_count_dev, root_count, flags_dev);
+                                                   prelist_count_dev, root_count, flags_dev, mask);
       KC_HIP(hipGetLastError());
     }
     if (emit) {
@@ -576,14 +578,15 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
       KC_TRY(scr.get(&toff, (size_t)n + 1));
       KC_TRY(scr.get(&ttot, 2));
       if (n > 0) {
-        k_pl_sizes<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, is_clique, comp_n, emit->cap, msz, tsz);
+        k_pl_sizes<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, is_clique, comp_n, emit->cap, mask, msz,
+                                               tsz);
         KC_HIP(hipGetLastError());
       }
       KC_TRY(kc_scan_i32(msz, moff, n, nullptr, scr, s));
       KC_TRY(kc_scan_i64(tsz, toff, n, ttot, scr, s));
       if (n > 0) {
         KC_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * (size_t)n, s));
-        k_pl_members<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, is_clique, moff, fill, members);
+        k_pl_members<<<grid_for(n), 256, 0, s>>>(n, out->removed, parent, is_clique, mask, moff, fill, members);
         k_pl_emit<<<1024, 256, 0, s>>>(n, k, vk, toff, moff, comp_n, members, ttot, *emit);
         KC_HIP(hipGetLastError());
       }
@@ -591,7 +594,7 @@ int kc_preprocess(const kc_dev_graph& g, int32_t k, const int32_t* vk, int32_t o
     }
     if (n > 0) {
       k_prelist_remove<<<grid_for(n), 256, 0, s>>>(n, k, vk, out->removed, parent, comp_n, is_clique, pv_dev,
-                                                    flags_dev);
+                                                    flags_dev, mask);
       KC_HIP(hipGetLastError());
     }
   }

@@ -3,6 +3,7 @@ function the public header declares (no GPU needed)."""
 import ctypes
 import os
 
+import numpy as np
 import pytest
 
 import paper_2203_13512_amd as kc
@@ -75,3 +76,17 @@ def _header_fields(struct_name):
 def test_binding_structs_follow_the_header_field_order():
     assert [f[0] for f in kc.Options._fields_] == _header_fields("kc_options")
     assert [f[0] for f in kc.Stats._fields_] == _header_fields("kc_stats")
+
+
+def test_root_mask_needs_a_graph_on_the_device():
+    """A root mask (kc_options.root_mask) is a device array; the binding
+    refuses it with host graph arrays before any call reaches the library."""
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    ci = np.array([1, 0], dtype=np.int32)
+    mask = np.ones(2, dtype=np.uint8)
+    with pytest.raises(ValueError):
+        kc.count(rp, ci, 3, "color", root_mask=mask)
+    with pytest.raises(ValueError):
+        kc.list_cliques(rp, ci, 3, "color", capacity=4, root_mask=mask)
+    with pytest.raises(ValueError):
+        kc.workspace_size(rp, ci, 3, "color", root_mask=mask)

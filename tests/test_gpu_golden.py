@@ -90,7 +90,9 @@ SAMPLED = sorted(glob.glob(os.path.join(G.GOLDEN, "sampled_w[0-9]_k*_color.json"
 def test_sampled_root_parity(path):
     """Workloads whose full enumeration is beyond the oracle: the cliques,
     BitJoins and words of the cheapest roots of the 8-, 12-, 16- and
-    24-word classes (tests/golden/make_sampled.py), from the whole GPU run."""
+    24-word classes (tests/golden/make_sampled.py), from the GPU run
+    restricted to those roots (kc_options.root_mask) and, where the whole
+    workload takes seconds (k <= 6), from the whole run."""
     gd = _load(path)
     w = G.workload_cached(gd["cfg"])
     rp_h, ci_h = w.graphs[0]
@@ -99,18 +101,28 @@ def test_sampled_root_parity(path):
     rp = torch.from_numpy(rp_h).cuda()
     ci = torch.from_numpy(ci_h).cuda()
     roots = np.asarray(gd["roots"], dtype=np.int64)
+    mask = torch.zeros(len(rp_h) - 1, dtype=torch.bool, device=rp.device)
+    mask[torch.from_numpy(roots).to(rp.device)] = True
     tuned = autotune.lookup(rp_h, ci_h, k, "color", schedule="learned")
     for kw in (dict(schedule="learned", mlp=scheduler.load_model(rp.device, k), **tuned), dict(schedule="degree")):
-        say(os.path.basename(path), {key: v for key, v in kw.items() if key != "mlp"})
-        c, st = kc.count(rp, ci, k, "color", root_logs=True, **kw)
-        lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
-        assert st["prelist_count"] == gd["prelist_count"]
-        assert np.array_equal(lg["features"][roots, 0].astype(np.int64), gd["out_degree"])
-        assert np.array_equal(lg["features"][roots, 1].astype(np.int64), gd["core"])
-        assert np.array_equal(lg["count"][roots], np.asarray(gd["count"], dtype=np.int64))
-        assert np.array_equal(lg["isect"][roots], np.asarray(gd["isect"], dtype=np.int64))
-        assert np.array_equal(lg["work"][roots], np.asarray(gd["words"], dtype=np.int64))
-        assert int(lg["count"].sum()) == c
+        for whole in ((False, True) if k <= 6 else (False,)):
+            say(os.path.basename(path), "whole run" if whole else "sampled roots only",
+                {key: v for key, v in kw.items() if key != "mlp"})
+            c, st = kc.count(rp, ci, k, "color", root_logs=True, root_mask=None if whole else mask, **kw)
+            lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
+            assert np.array_equal(lg["features"][roots, 0].astype(np.int64), gd["out_degree"])
+            assert np.array_equal(lg["features"][roots, 1].astype(np.int64), gd["core"])
+            assert np.array_equal(lg["count"][roots], np.asarray(gd["count"], dtype=np.int64))
+            assert np.array_equal(lg["isect"][roots], np.asarray(gd["isect"], dtype=np.int64))
+            assert np.array_equal(lg["work"][roots], np.asarray(gd["words"], dtype=np.int64))
+            assert int(lg["count"].sum()) == c
+            if whole:
+                assert st["prelist_count"] == gd["prelist_count"]
+            else:
+                # the sampled roots are DAG roots, none the smallest vertex of
+                # a clique component
+                assert st["n_roots"] == len(roots) and st["prelist_count"] == 0
+                assert c == sum(gd["count"])
 
 
 @pytest.mark.skipif(not os.path.exists(BATCH), reason="no stored batch counts")
