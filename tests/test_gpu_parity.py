@@ -239,7 +239,8 @@ def test_schedule_does_not_change_results(order):
 # root): off, one-word rows at every level, one-word rows from level 4 with
 # the level-2 queue, and two-word rows (sets of 65..128) when counting.
 REENCODE = [dict(compress=-1), dict(compress=64, compress_level=2), dict(compress=64, compress_level=4),
-            dict(compress=128, compress_level=4), dict(compress=128, compress_level=6, waves_per_root=1),
+            dict(compress=128, compress_level=4), dict(compress=128, compress_level=3),
+            dict(compress=128, compress_level=6, waves_per_root=1),
             dict(compress=100, compress_level=4, waves_per_root=4, split=2, split_threshold=1.0)]
 
 
