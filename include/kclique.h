@@ -119,8 +119,10 @@ typedef struct {
   int32_t schedule;       /* KC_SCHED_DEGREE (default) or KC_SCHED_LEARNED */
   const float* mlp_params;/* LEARNED: device pointer, KC_MLP_NPARAMS floats */
   const float* mlp_norm;  /* LEARNED: device pointer, 8 floats: feature mean[4], std[4] (of log1p features) */
-  int32_t waves_per_root; /* BitCol waves sharing one root's bitmaps: 0 = auto (8 for roots of more than 128
-                             out-neighbours, 4 above 64, else 1), 1, 4 or 8 (others round down) */
+  int32_t waves_per_root; /* BitCol waves sharing one root's bitmaps: 0 = auto (16 for roots of more than 512
+                             out-neighbours, 8 above 128, 4 above 64, else 1), 1, 4, 8 or 16 (others round
+                             down; 16 applies to the 24- and 32-word classes when counting, where one
+                             workgroup per CU is all the LDS holds, and means 8 elsewhere) */
   int32_t chunk;          /* tasks taken per queue access: 0 = auto */
   int32_t split;          /* heavy-root splitting: 0 = auto, -1 = never, 1/2 = force that depth for heavy roots */
   float split_threshold;  /* 0 = auto: schedule key above which roots are split */

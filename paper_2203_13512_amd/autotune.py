@@ -1,7 +1,7 @@
 """Autotuner for the launch shape of the BitCol listing kernels.
 
 Searched knobs (kc_options, GRID below): how many waves share one root's
-bitmaps in LDS (lanes per root: 64, 256 or 512), how many queue items a
+bitmaps in LDS (lanes per root: 64, 256, 512 or 1024), how many queue items a
 workgroup takes per access (chunking), up to which candidate-set size nodes
 are re-encoded into 64-bit rows and from which recursion level (the word
 width the deepest levels run on), and whether the word classes' kernels run
@@ -41,7 +41,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json"
 # re-encoded, and whether the word classes' kernels run in sequence or
 # concurrently.
 GRID = {
-    "waves_per_root": [0, 1, 4, 8],
+    "waves_per_root": [0, 1, 4, 8, 16],
     "chunk": [0, 1, 4, 16, 64],
     "compress": [0, 64, -1],
     "compress_level": [0, 3, 5],

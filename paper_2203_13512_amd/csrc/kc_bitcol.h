@@ -637,8 +637,11 @@ template <int L>
 __device__ __forceinline__ void wdfs(CQueue& Q, const uint64_t* __restrict__ cm, uint64_t R, uint64_t X,
                                      uint64_t top, int lane, uint64_t& joins, uint64_t& nodes) {
   if constexpr (L == 3) {
-    // level-3 node: lane z is candidate z
-    const bool cand = ((X & Q.c3 & top) >> lane) & 1ull;
+    // level-3 node: lane z is candidate z (a node without candidates adds
+    // nothing: its join and node counts and the queue stay as they are)
+    const uint64_t cands = X & Q.c3 & top;
+    if (!cands) return;
+    const bool cand = (cands >> lane) & 1ull;
     const uint64_t X2 = R & X;
     joins += cand ? 1u : 0u;
     const bool push = cand && __popcll(X2) >= 2;
@@ -743,8 +746,10 @@ __device__ __forceinline__ void wdfs2(CQueue2& Q, const uint64_t* __restrict__ c
                                       uint64_t R1h, uint64_t Xl, uint64_t Xh, uint64_t topl, uint64_t toph, int lane,
                                       uint64_t& joins, uint64_t& nodes) {
   if constexpr (L == 3) {
-    cq2_push(Q, ((Xl & Q.c3l & topl) >> lane) & 1ull, R0 & Xl, 0ull, lane, joins, nodes);
-    cq2_push(Q, ((Xh & Q.c3h & toph) >> lane) & 1ull, R1l & Xl, R1h & Xh, lane, joins, nodes);
+    // each half with candidates (children of members below 64 have no high half)
+    const uint64_t cl = Xl & Q.c3l & topl, ch = Xh & Q.c3h & toph;
+    if (cl) cq2_push(Q, (cl >> lane) & 1ull, R0 & Xl, 0ull, lane, joins, nodes);
+    if (ch) cq2_push(Q, (ch >> lane) & 1ull, R1l & Xl, R1h & Xh, lane, joins, nodes);
   } else {
     uint64_t cl = Xl & readfirstlane64(cm[2 * L]) & topl;
     uint64_t ch = Xh & readfirstlane64(cm[2 * L + 1]) & toph;
@@ -1337,8 +1342,14 @@ static int resolve_list(const ListArgs& a, ListLaunch* L) {
 
 template <int W, bool PV>
 static int resolve_list_nw(const ListArgs& a, int nw, ListLaunch* L) {
-  // fewer waves per root when the requested shape's LDS does not fit
+  // fewer waves per root when the requested shape's LDS does not fit.  The
+  // 24- and 32-word classes also run 16 waves per root: their bitmaps take
+  // most of a CU's LDS, so one workgroup per CU is all that fits, and 16
+  // waves give each SIMD four.
   const size_t lim = device_max_lds();
+  if constexpr (W >= 24 && !PV) {
+    if (nw >= 16 && list_lds_bytes<W, 16, PV, false>(a) <= lim) return resolve_list<W, 16, PV, false>(a, L);
+  }
   if (nw >= 8 && list_lds_bytes<W, 8, PV, false>(a) <= lim) return resolve_list<W, 8, PV, false>(a, L);
   if (nw >= 2 && list_lds_bytes<W, 4, PV, false>(a) <= lim) return resolve_list<W, 4, PV, false>(a, L);
   if (list_lds_bytes<W, 1, PV, false>(a) <= lim) return resolve_list<W, 1, PV, false>(a, L);

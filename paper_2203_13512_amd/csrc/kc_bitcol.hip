@@ -791,8 +791,9 @@ int kc_list_bitcol(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     la.tasks = tasks_sorted + lo;
     la.ntasks = hi - lo;
     la.head = heads + cl;
-    nws[cl] = opt && opt->waves_per_root > 0 ? opt->waves_per_root
-                                              : (kWClass[cl] >= 8 ? 8 : (kWClass[cl] >= 4 ? 4 : 1));
+    nws[cl] = opt && opt->waves_per_root > 0
+                  ? opt->waves_per_root
+                  : (kWClass[cl] >= 24 ? 16 : (kWClass[cl] >= 8 ? 8 : (kWClass[cl] >= 4 ? 4 : 1)));
     la.chunk = opt && opt->chunk > 0 ? opt->chunk : (kWClass[cl] >= 8 ? 1 : 8);
     la.k = c.k;
     la.vk = c.vk;

@@ -53,7 +53,8 @@ def classes_run(st):
 
 LAUNCH = [dict(), dict(waves_per_root=1), dict(waves_per_root=4, chunk=4), dict(compress=-1),
           dict(compress=64, compress_level=3), dict(split=1, split_threshold=1.0),
-          dict(split=2, split_threshold=1.0, waves_per_root=8), dict(class_streams=2)]
+          dict(split=2, split_threshold=1.0, waves_per_root=8), dict(class_streams=2),
+          dict(waves_per_root=16), dict(waves_per_root=16, split=2, split_threshold=1.0)]
 
 
 @pytest.mark.parametrize("k", [4, 5])
@@ -62,13 +63,17 @@ def test_every_word_class_complete_minus_edge(k):
     g = dev(G.complete_minus_edge(n))
     want = minus_edge_count(n, k)
     # every launch shape at k = 4; at k = 5 (40x the joins) three of them
+    base = None
     for kw in (LAUNCH if k == 4 else [dict(), dict(split=2, split_threshold=1.0, waves_per_root=8),
-                                      dict(class_streams=2)]):
+                                      dict(class_streams=2), dict(waves_per_root=16)]):
         say("K_n - e", n, k, kw)
         c, st = kc.count(*g, k, "color", stats=True, **kw)
         assert c == want, kw
         assert classes_run(st) == WORDS[:8], classes_run(st)
         assert st["max_out_degree"] == n - 2
+        # joins and nodes are the method's, whatever the launch shape
+        base = base or st
+        assert (st["isect"], st["nodes"]) == (base["isect"], base["nodes"]), kw
 
 
 def test_every_word_class_k6_and_learned_schedule():
