@@ -57,11 +57,11 @@ WORD_CLASSES = [1, 2, 4, 8, 12, 16, 24, 32, 48, 64]
 # 4M-vertex Chung-Lu workload at k = 8) from two profiler passes (FETCH_SIZE
 # and WRITE_SIZE, each scaled by what the same counter reads for a plain copy
 # of known size), valid only for the kernel sources they were taken on.
-PROFILED_TRAFFIC = {"sources_sha256_16": "51b0185cf18bbc74", "word_class": 16,
-                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 17.86e9,
+PROFILED_TRAFFIC = {"sources_sha256_16": "522a70ac328710ac", "word_class": 16,
+                    "workload": "chunglu_n4000000_d30_g2.0_planted", "k": 8, "bytes": 17.97e9,
                     "summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_hbm_counters.md",
                     # SQ_INSTS_VALU of the same launch and its duration in that run
-                    "valu_wave_insts": 8.330e12, "valu_launch_ms": 14144.9,
+                    "valu_wave_insts": 8.276e12, "valu_launch_ms": 14207.4,
                     "valu_summary": "profiles/k_bitcol_list_chunglu4M_d30_k8_sq_counters.md"}
 # one wave64 VALU instruction per CU per clock: 256 CUs at 2.4 GHz
 VALU_ISSUE_PEAK_PER_S = 256 * 2.4e9
