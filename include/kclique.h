@@ -64,8 +64,9 @@ typedef enum {
 #define KC_ORDER_DEGREE_REDUCED 3 /* SDegree with the out-neighbour reduction (Sec. 7.2): Alg. 5 runs on each
                                      root's DAG G_u induced by N+(u), whose out-lists are N+(x) restricted to
                                      N+(u); its pruning uses the out-degree in G_u and its logged work is
-                                     |C| + |L_x| per join.  Roots of more than 1024 out-neighbours give
-                                     KC_EUNSUPPORTED. */
+                                     |C| + |L_x| per join.  Roots of more than 4096 out-neighbours give
+                                     KC_EUNSUPPORTED (the reduced lists hold 16-bit positions of N+(u)
+                                     in a per-workgroup pool of d+(d+ - 1)/2 entries). */
 #define KC_ORDER_CORE_REDUCED 4   /* the same on the degeneracy order */
 
 /* Ablations (kc_options.disable, bit mask; Sec. 9.2 and 9.4 compare the

@@ -971,9 +971,10 @@ int kc_list_sdegree(kc_list_ctx& c, kc_scratch& scr, hipStream_t st) {
     a.pool = nullptr;
     a.pool_cap = 0;
     if (c.reduce) {
-      // G_u of up to 1088 vertices (the 1024-entry class): the reduced lists,
-      // at most SM (SM - 1) / 2 entries, in a per-workgroup pool
-      if (cl >= 3) return KC_EUNSUPPORTED;
+      // G_u of up to 4096 vertices (the 4096-entry class; positions are
+      // 16-bit): the reduced lists, at most SM (SM - 1) / 2 entries, in a
+      // per-workgroup pool (16 MiB per workgroup at 4096)
+      if (cl >= 4) return KC_EUNSUPPORTED;
       const size_t rbytes = 4 * sdr_words(c.k, a.SMAX, pv);
       int dev = 0, maxlds = 65536;
       KC_HIP(hipGetDevice(&dev));

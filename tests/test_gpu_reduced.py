@@ -4,9 +4,11 @@
 Counts equal the definition; per-root joins, Lemma-2 work (|C| + |L_x| per
 join on G_u) and node counts equal the oracle's reduced recursion, for whole
 roots and for roots split into edge tasks, with and without pruning;
-per-vertex participation and the listing equal the oracle's.  Roots beyond
-its 1024-entry lists are refused, not approximated.
+per-vertex participation and the listing equal the oracle's, also for roots
+of the 4096-entry list class.  Roots beyond it are refused, not
+approximated.
 """
+import math
 import sys
 
 import numpy as np
@@ -103,9 +105,66 @@ def test_reduced_per_vertex_and_listing(order):
                 assert np.array_equal(got[np.lexsort(got.T[::-1])], np.asarray(exp, dtype=np.int32))
 
 
+def _bipartite_with_clique_np(a, b, m):
+    """G.bipartite_with_clique built with numpy (for sizes where a Python
+    edge list is slow)."""
+    left = np.repeat(np.arange(a, dtype=np.int32), b)
+    right = np.tile(np.arange(a, a + b, dtype=np.int32), a)
+    iu, ju = np.triu_indices(m, 1)
+    clique = np.stack([iu + a, ju + a], axis=1).astype(np.int32)
+    return graphgen.from_edges(a + b, np.concatenate([np.stack([left, right], axis=1), clique]))
+
+
+@pytest.mark.parametrize("order", ["degree_reduced", "core_reduced"])
+def test_reduced_roots_of_the_4096_entry_class(order):
+    """Roots of 1025..4096 out-neighbours (the 4096-entry list class):
+    K_{1100,1100} plus a 9-clique on the right.  In degree order every left
+    vertex has the 1100 right vertices as out-neighbours.  Counts, per-vertex
+    values, listing and per-root logs equal the oracle's."""
+    g = G.bipartite_with_clique(1100, 1100, 9)
+    rp, ci = dev(g)
+    for k in (3, 4, 5):
+        want, wpv = oracle.count(*g, k, per_vertex=True)
+        total, pl, per = oracle.method_count(*g, k, order)
+        assert total == want == 1100 * math.comb(9, k - 1) + math.comb(9, k)
+        roots = per["dplus"] >= k - 1
+        for kw in (dict(), dict(split=1, split_threshold=1.0), dict(disable=kc.NO_PRUNE)):
+            say("4096-entry class", order, k, kw)
+            if "disable" in kw:
+                total, pl, per = oracle.method_count(*g, k, order, disable=kw["disable"])
+            c, st = kc.count(rp, ci, k, order, root_logs=True, **kw)
+            assert c == want, kw
+            assert st["max_out_degree"] > 1024 and st["class_tasks"][3] > 0
+            lg = {key: v.cpu().numpy() for key, v in st["root_logs"].items()}
+            assert np.array_equal(lg["count"][roots], per["count"][roots].astype(np.int64)), kw
+            assert np.array_equal(lg["isect"], per["isect"].astype(np.int64)), kw
+            assert np.array_equal(lg["work"], per["work"].astype(np.int64)), kw
+            assert st["nodes"] == int(per["nodes"].sum())
+        c, pv = kc.count(rp, ci, k, order, per_vertex=True)
+        assert c == want and np.array_equal(pv.cpu().numpy(), wpv.astype(np.int64))
+        rows, t = kc.list_cliques(rp, ci, k, order)
+        assert t == want
+        got = np.sort(rows.cpu().numpy(), axis=1)
+        exp, _ = oracle.list_cliques(*g, k)
+        assert np.array_equal(got[np.lexsort(got.T[::-1])], np.asarray(exp, dtype=np.int32))
+
+
+def test_reduced_dense_4096_entry_class_closed_form():
+    """K_1030 minus one edge: roots of up to 1028 out-neighbours whose G_u are
+    dense (the pool holds about d+^2/2 entries); C(n,k) - C(n-2,k-2)."""
+    n = 1030
+    big = dev(G.complete_minus_edge(n))
+    for order in ("degree_reduced", "core_reduced"):
+        say("K_n - e, reduced", order)
+        c, st = kc.count(*big, 4, order, stats=True)
+        assert c == math.comb(n, 4) - math.comb(n - 2, 2)
+        assert st["class_tasks"][3] > 0
+
+
 def test_reduced_roots_beyond_its_lists_are_refused():
-    # out-degrees above 1024 (the 4096-entry list class)
-    big = dev(G.complete_minus_edge(1030))
+    # out-degrees above 4096 (the 16384-entry list class): K_{4100,4100}
+    # plus a 5-clique on the right, so that its roots have work
+    big = dev(_bipartite_with_clique_np(4100, 4100, 5))
     with pytest.raises(kc.KCliqueError) as e:
         kc.count(*big, 4, "degree_reduced")
     assert e.value.status == kc.EUNSUPPORTED
