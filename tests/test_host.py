@@ -99,3 +99,18 @@ def test_generators_are_deterministic_and_follow_the_recipe():
     for (rp, ci), (n, d, k) in zip(w4.graphs, w4.params["graphs"]):
         assert len(rp) - 1 == n and oracle.validate(rp, ci)
         assert abs(len(ci) / n - d) < 0.5 * d  # mean degree near its draw
+
+
+def test_root_shares_partition_the_vertices():
+    """paper_2203_13512_amd.shares assigns every vertex to exactly one of S
+    shares by a multiplicative hash of its id; consecutive ids (and the
+    low-id hubs of R-MAT graphs) spread over all shares."""
+    torch = pytest.importorskip("torch")
+    from paper_2203_13512_amd import shares
+    n, S = 100_003, 16
+    idx = shares.share_index(n, S, torch.device("cpu")).numpy()
+    assert idx.shape == (n,) and idx.min() >= 0 and idx.max() < S
+    counts = np.bincount(idx, minlength=S)
+    assert counts.sum() == n and counts.min() > 0.95 * n / S and counts.max() < 1.05 * n / S
+    assert len(set(idx[:64].tolist())) == S  # the first 64 ids reach every share
+    assert np.array_equal(shares.share_index(n, 1, torch.device("cpu")).numpy(), np.zeros(n, dtype=np.int64))
