@@ -14,7 +14,10 @@ For each it runs the oracle's BitCol (Alg. 6) from that root alone and
 records the cliques listed from it, its BitJoins and its words.  Output:
 ``sampled_w<workload>_k<k>_color.json``.
 
-Usage: python tests/golden/make_sampled.py [--per N] [--procs P] JOB [JOB ...]
+Usage: python tests/golden/make_sampled.py [--per N] [--procs P] [--classes 8,12,16,24] JOB [JOB ...]
+
+The file is rewritten as roots finish (in the order of the picks), so a run
+cut short keeps the roots it completed.
 """
 from __future__ import annotations
 
@@ -35,7 +38,7 @@ sys.path.insert(0, ROOT)
 import graphgen  # noqa: E402
 import oracle  # noqa: E402
 
-CLASSES = [(128, 256), (256, 384), (384, 512), (512, 768)]
+CLASSES = {8: (128, 256), 12: (256, 384), 16: (384, 512), 24: (512, 768)}
 _JOB = None
 
 
@@ -50,6 +53,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--per", type=int, default=4)
     ap.add_argument("--procs", type=int, default=4)
+    ap.add_argument("--classes", default="8,12,16,24", help="word classes to sample")
     ap.add_argument("jobs", nargs="+")
     args = ap.parse_args()
     for job in args.jobs:
@@ -62,27 +66,31 @@ def main():
         drp, dci, _, core = oracle.degeneracy_dag(rp, ci, removed)
         dp = np.diff(drp)
         picks = []
-        for lo, hi in CLASSES:
+        for c in (int(x) for x in args.classes.split(",")):
+            lo, hi = CLASSES[c]
             cls = np.flatnonzero((dp > lo) & (dp <= hi))
             picks += [int(r) for r in cls[np.lexsort((cls, core[cls]))][: args.per]]
         _JOB = (drp, dci, k)
-        with mp.get_context("fork").Pool(args.procs) as pool:
-            res = pool.map(_one, picks)
         h = hashlib.sha256()
         h.update(np.ascontiguousarray(rp, dtype="<i4").tobytes())
         h.update(np.ascontiguousarray(ci, dtype="<i4").tobytes())
-        out = {
-            "workload": w.name, "cfg": cfg, "k": k, "order": "color", "n": int(len(rp) - 1),
-            "nnz": int(len(ci)), "graph_sha256": h.hexdigest(), "prelist_count": pl,
-            "roots": [r[0] for r in res], "out_degree": [int(dp[r[0]]) for r in res],
-            "core": [int(core[r[0]]) for r in res], "count": [r[1] for r in res],
-            "isect": [r[2] for r in res], "words": [r[3] for r in res],
-            "oracle_seconds": round(time.time() - t0, 1), "oracle_processes": args.procs,
-        }
         path = os.path.join(HERE, f"sampled_w{cfg}_k{k}_color.json")
-        with open(path, "w") as f:
-            json.dump(out, f, indent=1)
-        print(path, out["oracle_seconds"], "s", flush=True)
+        done = {}
+        with mp.get_context("fork").Pool(args.procs) as pool:
+            for r in pool.imap_unordered(_one, picks):
+                done[r[0]] = r
+                res = [done[p] for p in picks if p in done]
+                out = {
+                    "workload": w.name, "cfg": cfg, "k": k, "order": "color", "n": int(len(rp) - 1),
+                    "nnz": int(len(ci)), "graph_sha256": h.hexdigest(), "prelist_count": pl,
+                    "roots": [r[0] for r in res], "out_degree": [int(dp[r[0]]) for r in res],
+                    "core": [int(core[r[0]]) for r in res], "count": [r[1] for r in res],
+                    "isect": [r[2] for r in res], "words": [r[3] for r in res],
+                    "oracle_seconds": round(time.time() - t0, 1), "oracle_processes": args.procs,
+                }
+                with open(path, "w") as f:
+                    json.dump(out, f, indent=1)
+                print(path, len(res), "of", len(picks), "roots", out["oracle_seconds"], "s", flush=True)
 
 
 if __name__ == "__main__":
