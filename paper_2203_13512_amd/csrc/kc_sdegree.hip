@@ -34,6 +34,9 @@
 #include "kc_internal.h"
 
 #define SD_NCLASS 6
+// out-lists of at most this many entries are read whole by a join instead of
+// locating the range that can match by binary search
+#define SD_WHOLE_LIST 64
 static const int kSClass[SD_NCLASS] = {64, 256, 1024, 4096, 16384, 65536};
 
 __device__ __forceinline__ int sd_class_of(int s) {
@@ -196,15 +199,22 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
               if (dx > 0 || a.noprune) {
                 my_isect++;
                 my_work += (uint64_t)sz + (uint64_t)dx;
-                int l0 = xb, h0 = xe;
-                while (l0 < h0) {
-                  const int mid = (l0 + h0) >> 1;
-                  if (a.dcol[mid] < cmin) l0 = mid + 1; else h0 = mid;
-                }
-                int l1 = l0, h1 = xe;
-                while (l1 < h1) {
-                  const int mid = (l1 + h1) >> 1;
-                  if (a.dcol[mid] <= cmax) l1 = mid + 1; else h1 = mid;
+                // a short list is taken whole (its entries outside
+                // [min C, max C] find no match): one load instead of two
+                // chains of dependent loads
+                int l0 = xb, l1 = xe;
+                if (dx > SD_WHOLE_LIST) {
+                  int h0 = xe;
+                  while (l0 < h0) {
+                    const int mid = (l0 + h0) >> 1;
+                    if (a.dcol[mid] < cmin) l0 = mid + 1; else h0 = mid;
+                  }
+                  l1 = l0;
+                  int h1 = xe;
+                  while (l1 < h1) {
+                    const int mid = (l1 + h1) >> 1;
+                    if (a.dcol[mid] <= cmax) l1 = mid + 1; else h1 = mid;
+                  }
                 }
                 lo = l0;
                 len = l1 - l0;
@@ -271,9 +281,9 @@ __global__ __launch_bounds__(64) void k_sdegree_list(SdArgs a) {
         my_work += lane == 0 ? (uint64_t)sz + (uint64_t)dx : 0u;
         // merge join N+(x) with C
         const int32_t cmin = C[0], cmax = C[sz - 1];
-        // first entry of N+(x) that can match
-        int start;
-        {
+        // first entry of N+(x) that can match (a short list is read whole)
+        int start = xb;
+        if (dx > SD_WHOLE_LIST) {
           int lo = xb, hi = xe;
           while (lo < hi) {
             int mid = (lo + hi) >> 1;
@@ -410,15 +420,19 @@ __device__ void sdr_stage(const SdArgs& a, const int32_t* ids, int s, const uint
       ci = cand[idx];
       const int32_t x = ids[ci];
       const int32_t xb = a.drp[x], xe = a.drp[x + 1];
-      int l0 = xb, h0 = xe;
-      while (l0 < h0) {
-        const int mid = (l0 + h0) >> 1;
-        if (a.dcol[mid] < vmin) l0 = mid + 1; else h0 = mid;
-      }
-      int l1 = l0, h1 = xe;
-      while (l1 < h1) {
-        const int mid = (l1 + h1) >> 1;
-        if (a.dcol[mid] <= vmax) l1 = mid + 1; else h1 = mid;
+      int l0 = xb, l1 = xe;
+      if (xe - xb > SD_WHOLE_LIST) {  // a short list is taken whole
+        int h0 = xe;
+        while (l0 < h0) {
+          const int mid = (l0 + h0) >> 1;
+          if (a.dcol[mid] < vmin) l0 = mid + 1; else h0 = mid;
+        }
+        l1 = l0;
+        int h1 = xe;
+        while (l1 < h1) {
+          const int mid = (l1 + h1) >> 1;
+          if (a.dcol[mid] <= vmax) l1 = mid + 1; else h1 = mid;
+        }
       }
       lo = l0;
       len = l1 - l0;
