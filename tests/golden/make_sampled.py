@@ -14,7 +14,7 @@ For each it runs the oracle's BitCol (Alg. 6) from that root alone and
 records the cliques listed from it, its BitJoins and its words.  Output:
 ``sampled_w<workload>_k<k>_color.json``.
 
-Usage: python tests/golden/make_sampled.py [--per N] [--procs P] [--classes 8,12,16,24] JOB [JOB ...]
+Usage: python tests/golden/make_sampled.py [--per N] [--procs P] [--classes 8,12,16,24] [--tag T] JOB [JOB ...]
 
 The file is rewritten as roots finish (in the order of the picks), so a run
 cut short keeps the roots it completed.
@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--per", type=int, default=4)
     ap.add_argument("--procs", type=int, default=4)
     ap.add_argument("--classes", default="8,12,16,24", help="word classes to sample")
+    ap.add_argument("--tag", default="", help="written to sampled_w<workload>_k<k>_<tag>_color.json")
     ap.add_argument("jobs", nargs="+")
     args = ap.parse_args()
     for job in args.jobs:
@@ -74,7 +75,7 @@ def main():
         h = hashlib.sha256()
         h.update(np.ascontiguousarray(rp, dtype="<i4").tobytes())
         h.update(np.ascontiguousarray(ci, dtype="<i4").tobytes())
-        path = os.path.join(HERE, f"sampled_w{cfg}_k{k}_color.json")
+        path = os.path.join(HERE, f"sampled_w{cfg}_k{k}{'_' + args.tag if args.tag else ''}_color.json")
         done = {}
         with mp.get_context("fork").Pool(args.procs) as pool:
             for r in pool.imap_unordered(_one, picks):
