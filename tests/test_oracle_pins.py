@@ -619,3 +619,20 @@ def test_ablations_and_orders_reach_the_definition(seed):
                 if method in ("core", "core_reduced"):
                     d = base[2]["dplus"]
                     assert np.all(d <= np.maximum(core, 0))
+
+
+@pytest.mark.parametrize("method", ["degree", "color", "core", "degree_reduced"])
+def test_per_root_counts_partition_the_cliques(method):
+    """Theorem 1: every k-clique has one root, so the oracle's per-root
+    counts plus Pre-List's C(n_c, k) per clique component sum to the
+    definition's count, and the cliques of a root all contain it (a root's
+    count is at most its brute-force participation)."""
+    g = G.disjoint_union([G.complete(9), graphgen.erdos_renyi(40, 0.45, seed=11), G.complete(6)])
+    for k in (3, 4, 5):
+        want, pv = oracle.count(*g, k, per_vertex=True)
+        total, pl, per = oracle.method_count(*g, k, method)
+        roots = per["dplus"] >= k - 1
+        # the two clique components, removed by Pre-List
+        assert pl == math.comb(9, k) + math.comb(6, k)
+        assert total == want == int(per["count"][roots].astype(np.uint64).sum()) + pl
+        assert np.all(per["count"][roots].astype(np.int64) <= pv[roots].astype(np.int64))
