@@ -44,10 +44,15 @@ def count_in_shares(row_ptr, col_idx, k: int, order: str = "color", shares: int 
     import paper_2203_13512_amd as kc
     if shares < 1:
         raise ValueError("shares must be >= 1")
+    which = list(range(shares) if which is None else which)
+    if any(not 0 <= s < shares for s in which):
+        raise ValueError(f"share indices must lie in [0, {shares})")
+    if "stats" in kw or "root_mask" in kw:
+        raise TypeError("count_in_shares sets stats and root_mask itself")
     n = row_ptr.numel() - 1
     idx = share_index(n, shares, row_ptr.device)
     out = []
-    for s in (range(shares) if which is None else which):
+    for s in which:
         mask = idx == s
         torch.cuda.synchronize(row_ptr.device)
         t = time.perf_counter()
